@@ -1,0 +1,75 @@
+"""The seeded input generators: determinism, the shapes each instance promises,
+and (on a GPU) bit-identical columns on the CPU and the GPU."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+
+def test_deterministic_and_seeded():
+    a = synth.plain_dense(seed=1, n_build=1000, n_probe=5000)
+    b = synth.plain_dense(seed=1, n_build=1000, n_probe=5000)
+    c = synth.plain_dense(seed=2, n_build=1000, n_probe=5000)
+    for x, y in [(a.build_keys, b.build_keys), (a.probe_keys, b.probe_keys),
+                 (a.probe_payload, b.probe_payload)]:
+        assert torch.equal(x, y)
+    assert not torch.equal(a.build_keys, c.build_keys)
+
+
+def test_plain_dense_shape():
+    inp = synth.plain_dense(seed=42, n_build=65536, n_probe=1 << 20)
+    assert torch.equal(torch.sort(inp.build_keys).values, torch.arange(65536, dtype=torch.int32))
+    pk = inp.probe_keys
+    assert int(pk.min()) >= 0 and int(pk.max()) < 81920
+    assert abs(float((pk < 65536).float().mean()) - 0.8) < 0.005
+    assert int(inp.build_payload.min()) >= 0 and int(inp.build_payload.max()) < 1000
+
+
+def test_sparse_unique64_shape():
+    inp = synth.sparse_unique64(seed=42, n_build=100000, n_probe=300000)
+    bk = inp.build_keys.numpy()
+    assert np.unique(bk).size == bk.size
+    src = inp.meta["source_row"].numpy()
+    pk = inp.probe_keys.numpy()
+    hit = src >= 0
+    assert np.array_equal(pk[hit], bk[src[hit]])
+    assert not np.isin(pk[~hit], bk).any()
+    assert abs(hit.mean() - 0.9) < 0.005
+
+
+def test_skewed_dup32_shape():
+    inp = synth.skewed_dup32(seed=42, n_distinct=20000, n_probe=200000, zipf_s=1.5)
+    bk = inp.build_keys.numpy()
+    vals, cnt = np.unique(bk, return_counts=True)
+    assert vals.size == 20000 and vals.min() >= 0
+    assert abs(cnt.mean() - 4.0) < 0.1
+    assert np.isin(inp.probe_keys.numpy(), vals).all()
+    # Zipf(1.5): the top rank takes 1/H(n, 1.5) of the probes
+    h = np.sum(np.arange(1, 20001, dtype=np.float64) ** -1.5)
+    top = np.unique(inp.probe_keys.numpy(), return_counts=True)[1].max() / 200000
+    assert abs(top - 1 / h) < 0.01
+
+
+def test_geometric_mean_four():
+    r = synth.rand64(3, 1, torch.arange(400000))
+    d = synth.geometric(r, synth.geometric_table())
+    assert int(d.min()) == 1
+    assert abs(float(d.double().mean()) - 4.0) < 0.03
+
+
+def test_bij31_is_injective_on_a_range():
+    x = synth.bij31(torch.arange(1 << 20), seed=11)
+    assert int(x.min()) >= 0 and int(x.max()) < (1 << 31)
+    assert torch.unique(x).numel() == 1 << 20
+
+
+@pytest.mark.gpu
+def test_generators_identical_on_gpu(gpu):
+    for make in (lambda d: synth.plain_dense(seed=5, n_build=5000, n_probe=20000, device=d),
+                 lambda d: synth.sparse_unique64(seed=5, n_build=5000, n_probe=20000, device=d),
+                 lambda d: synth.skewed_dup32(seed=5, n_distinct=3000, n_probe=20000, zipf_s=1.0,
+                                              device=d)):
+        a, b = make("cpu"), make(gpu)
+        for f in ("build_keys", "build_payload", "probe_keys", "probe_payload"):
+            assert torch.equal(getattr(a, f), getattr(b, f).cpu()), f
