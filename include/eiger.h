@@ -1,0 +1,210 @@
+/*
+ * eiger.h -- C ABI of the MI355X (gfx950) equi-join library.
+ *
+ * The library implements the runtime-adaptive equi-join of "Eiger: An
+ * Efficient Library for GPU-based Data Analytics": lightweight statistics of
+ * a key column (min, max and an HLL++-style distinct-count sketch, Section 4
+ * and Section 4.1), a choice of join variant and knobs from those statistics
+ * (Section 4, "algorithm selection"; join factors in Table 1), and an inner
+ * equi-join that returns matched row-id pairs (late materialization through
+ * tuple ids, Section 2.2) plus a payload aggregate, the "narrow join" of
+ * Section 5.2.1 whose materialization is inlined into the join.
+ *
+ * Conventions shared by every entry point:
+ *  - Data pointers marked DEVICE point to GPU memory owned by the caller; the
+ *    library never allocates, frees or keeps them. HOST pointers are ordinary
+ *    host memory owned by the caller.
+ *  - Scratch memory is the caller's: size it with the *_workspace_size call
+ *    and pass it as (ws, ws_bytes). Its contents on entry do not matter and
+ *    are unspecified on return.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is ordered on that stream. Calls that return host values
+ *    synchronize the stream before returning.
+ *  - Every call returns an eiger_status; on failure eiger_last_error() holds
+ *    a message for the calling thread. No C++ exception crosses the ABI.
+ *  - Row ids are uint32: a column may hold at most 2^32 - 1 rows
+ *    (EIGER_ERR_TOO_LARGE beyond that). Counts and sizes are int64.
+ *  - Calls on different streams may run concurrently when each has its own
+ *    workspace and outputs.
+ */
+#ifndef EIGER_H
+#define EIGER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EIGER_OK = 0,
+    EIGER_ERR_INVALID_ARG = -1, /* null pointer, negative size, bad enum value */
+    EIGER_ERR_DTYPE = -2,       /* unsupported dtype or key dtypes that differ */
+    EIGER_ERR_TOO_LARGE = -3,   /* more than 2^32 - 1 rows, or a table beyond its limit */
+    EIGER_ERR_CAPACITY = -4,    /* output capacity below the result size; count is set */
+    EIGER_ERR_WORKSPACE = -5,   /* ws_bytes below the size the *_workspace_size call gives */
+    EIGER_ERR_HIP = -6,         /* a HIP runtime call failed (message has the HIP error) */
+    EIGER_ERR_UNSUPPORTED = -7, /* a plan the library cannot run (e.g. DIRECT over a huge range) */
+    EIGER_ERR_MODEL = -8        /* learned selector: no model loaded, or a malformed model */
+} eiger_status;
+
+typedef enum { EIGER_INT32 = 0, EIGER_INT64 = 1 } eiger_dtype;
+
+/* A column: `n` values of `dtype` at DEVICE address `data` (may be NULL when n == 0). */
+typedef struct {
+    const void *data;
+    int64_t n;
+    int32_t dtype;
+    int32_t reserved;
+} eiger_column;
+
+#define EIGER_HLL_P 14                 /* 2^14 one-byte registers */
+#define EIGER_HLL_REGISTERS (1 << EIGER_HLL_P)
+#define EIGER_STATS_EMPTY 1u           /* flag: the column has no rows */
+
+/*
+ * Statistics of one key column (Section 4: min and max of intermediate data;
+ * Section 4.1: an HLL++ sketch for the number of distinct values).
+ * min/max are the sign-extended key values (0 and 0 for an empty column).
+ * ndv is the distinct-count estimate from the 2^14 dense registers.
+ */
+typedef struct {
+    int64_t n;
+    int64_t min;
+    int64_t max;
+    double ndv;
+    int32_t dtype;
+    int32_t hll_p;
+    uint32_t flags;
+    uint32_t reserved;
+} eiger_stats_t;
+
+/* Join variants (Table 1 lists the paper's join algorithms; DIRECT is this
+ * library's addition for dense key ranges). */
+typedef enum {
+    EIGER_DIRECT = 0,      /* table indexed by key - min; needs a dense build key range */
+    EIGER_GLOBAL_HASH = 1, /* one open-addressing table in HBM (non-partitioned hash join) */
+    EIGER_RADIX = 2        /* hash-radix partitioning, then LDS-resident tables per partition */
+} eiger_variant;
+
+typedef enum {
+    EIGER_SEL_RULE = 0,       /* rule from the statistics (cardinalities, range, distinct count) */
+    EIGER_SEL_LEARNED = 1,    /* the loaded MLP selector (eiger_selector_load) */
+    EIGER_SEL_FIXED_HASH = 2, /* always GLOBAL_HASH at load factor 0.5 (a fixed-choice baseline) */
+    EIGER_SEL_FORCED = 3      /* take variant and knobs from `forced`, fill the rest */
+} eiger_selector;
+
+/*
+ * A join plan. eiger_join_plan fills it; callers may also build one by hand
+ * through EIGER_SEL_FORCED. Fields:
+ *  variant      eiger_variant
+ *  radix_bits   RADIX: total partition bits (fan-out 2^radix_bits), 1..18
+ *  radix_passes RADIX: 1 or 2 partitioning passes over each side
+ *  load_factor  GLOBAL_HASH / RADIX: target occupancy of a table, (0, 0.9]
+ *  key_dtype    dtype of both key columns
+ *  build_min/max  DIRECT: range of the build keys (from the build statistics)
+ *  predicted_out  estimated result size |R||S| / max(ndv_R, ndv_S) (informational)
+ */
+typedef struct {
+    int32_t variant;
+    int32_t radix_bits;
+    int32_t radix_passes;
+    int32_t key_dtype;
+    float load_factor;
+    uint32_t flags;
+    int64_t build_min;
+    int64_t build_max;
+    int64_t predicted_out;
+    int64_t reserved[4];
+} eiger_plan_t;
+
+/* ---- statistics ------------------------------------------------------------ */
+
+/* Workspace bytes eiger_stats needs for a column of n rows of dtype. */
+size_t eiger_stats_workspace_size(int64_t n, int32_t dtype);
+
+/*
+ * Count, min, max and distinct estimate of a key column in one pass over it
+ * (Section 4 / Section 4.1). Each key is sign-extended to 64 bits and hashed
+ * with MurmurHash3's fmix64; the top 14 bits pick a register, which keeps the
+ * largest rank (1 + leading zeros of the remaining 50 bits, 51 if all zero).
+ *  keys          DEVICE column, int32 or int64
+ *  out           HOST, filled on success
+ *  hll_regs_host HOST, 2^14 bytes receiving the registers, or NULL
+ *  ws, ws_bytes  DEVICE workspace of eiger_stats_workspace_size(keys.n, dtype)
+ * Synchronizes `stream`.
+ */
+int eiger_stats(eiger_column keys, eiger_stats_t *out, uint8_t *hll_regs_host,
+                void *ws, size_t ws_bytes, void *stream);
+
+/* ---- planning (host only, no GPU work) -------------------------------------- */
+
+/*
+ * Choose a variant and its knobs from the two sides' statistics (Section 4:
+ * runtime statistics drive algorithm selection; Table 1 names cardinalities,
+ * key distribution and match ratio as the join's runtime factors).
+ *  selector  eiger_selector
+ *  forced    HOST, used with EIGER_SEL_FORCED (variant, radix_bits,
+ *            radix_passes, load_factor taken from it), else may be NULL
+ *  out       HOST, the plan
+ */
+int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *probe, int32_t selector,
+                    const eiger_plan_t *forced, eiger_plan_t *out);
+
+/* ---- join ------------------------------------------------------------------- */
+
+/* Workspace bytes eiger_join needs for this plan and these columns (data
+ * pointers are not read). Writes the size to *bytes. */
+int eiger_join_workspace_size(const eiger_plan_t *plan, eiger_column build_keys,
+                              eiger_column build_payload, eiger_column probe_keys,
+                              eiger_column probe_payload, size_t *bytes);
+
+/*
+ * Inner equi-join of build side R and probe side S (Section 3.2 / Section 5.2).
+ * Result: every (i, j) with build_keys[i] == probe_keys[j], written as
+ * out_build_rowid[t] = i, out_probe_rowid[t] = j for t < count, in no
+ * particular order; *out_count = number of pairs; *out_checksum = sum over the
+ * pairs of build_payload[i] * probe_payload[j], payloads sign-extended to 64
+ * bits, products and sum mod 2^64, as int64.
+ *  build_*, probe_*  DEVICE columns; keys share a dtype; payload dtypes free;
+ *                    each payload column has as many rows as its key column
+ *  plan              HOST, from eiger_join_plan (or EIGER_SEL_FORCED)
+ *  out_*_rowid       DEVICE uint32 arrays of out_capacity entries, or both
+ *                    NULL with out_capacity == 0 (count-only mode)
+ *  out_count, out_checksum  HOST
+ * If the result has more than out_capacity pairs, returns EIGER_ERR_CAPACITY
+ * with *out_count = the exact pair count and *out_checksum set; the output
+ * arrays then hold an unspecified subset. Synchronizes `stream`.
+ */
+int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column probe_keys,
+               eiger_column probe_payload, const eiger_plan_t *plan, uint32_t *out_build_rowid,
+               uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
+               int64_t *out_checksum, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- diagnostics -------------------------------------------------------------- */
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *eiger_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int eiger_version(void);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around each
+ * kernel the library launches. Off by default; enabling it clears the table. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} eiger_kernel_time_t;
+
+int eiger_profile_enable(int on);
+/* Copies up to max_entries rows into HOST `out`, sets *n_out to the number of
+ * distinct kernels seen. Resolves pending events (synchronizes them). */
+int eiger_profile_read(eiger_kernel_time_t *out, int max_entries, int *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIGER_H */

@@ -1,0 +1,152 @@
+// join_hash.hip -- GLOBAL_HASH variant: one open-addressing table in HBM.
+//
+// This is the non-partitioned hash join of the paper (Section 3.2, Table 1),
+// laid out for gfx950: the key, row id and payload of a build row share one
+// 16-byte slot (32 bytes when key and payload are both 8 bytes), so a probe
+// touches one cache line per slot group instead of gathering keys through
+// tuple ids (the cost the paper blames for the hash join's losses, Section
+// 5.2.1). Slots are claimed by CAS on the row-id word (empty = 0xFFFFFFFF), so
+// no key value is reserved as a sentinel. The table is a multiset: duplicate
+// build keys occupy several slots and a probe walks the whole cluster (linear
+// probing) until an empty slot.
+#include "join_common.hpp"
+#include "variants.hpp"
+
+namespace eiger {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kIPT = 8;
+constexpr int kSCAP = 4096;
+
+template <typename K, typename P>
+struct alignas((sizeof(K) + sizeof(P) + 4 <= 16) ? 16 : 32) Slot {
+  K key;
+  uint32_t rowid;
+  P pay;
+};
+
+template <typename K, typename PB>
+struct HashTab {
+  const Slot<K, PB> *__restrict__ slots;
+  uint64_t mask;
+
+  __device__ __forceinline__ uint32_t lookup(K key, uint32_t &first, uint64_t &psum) const {
+    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
+    uint32_t c = 0;
+    for (;;) {
+      const Slot<K, PB> s = slots[i];
+      if (s.rowid == kEmpty) break;
+      if (s.key == key) {
+        first = s.rowid;
+        psum += static_cast<uint64_t>(sext(s.pay));
+        ++c;
+      }
+      i = (i + 1) & mask;
+    }
+    return c;
+  }
+  template <class F>
+  __device__ __forceinline__ void for_each(K key, F f) const {
+    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
+    for (;;) {
+      const Slot<K, PB> s = slots[i];
+      if (s.rowid == kEmpty) break;
+      if (s.key == key) f(s.rowid);
+      i = (i + 1) & mask;
+    }
+  }
+};
+
+template <typename K, typename PB>
+__global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ pay, uint64_t n,
+                             Slot<K, PB> *__restrict__ slots, uint64_t mask) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const K key = keys[r];
+    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
+    // The table has more slots than rows, so an empty slot is always found.
+    for (;;) {
+      if (atomicCAS(&slots[i].rowid, kEmpty, static_cast<uint32_t>(r)) == kEmpty) {
+        slots[i].key = key;
+        slots[i].pay = pay[r];
+        break;
+      }
+      i = (i + 1) & mask;
+    }
+  }
+}
+
+template <class Tab, typename K, typename PS>
+__global__ void __launch_bounds__(kNT) k_probe(Tab tab, const K *__restrict__ pk,
+                                               const PS *__restrict__ pp, uint64_t n, EmitOut o) {
+  __shared__ EmitLds<kNT, kSCAP> L;
+  uint32_t fill = 0;
+  uint64_t cs = 0;
+  constexpr uint64_t tile = uint64_t(kNT) * kIPT;
+  const uint64_t ntiles = (n + tile - 1) / tile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t lo = t * tile;
+    const uint64_t hi = lo + tile < n ? lo + tile : n;
+    probe_tile<kNT, kIPT, kSCAP>(tab, pk, pp, static_cast<const uint32_t *>(nullptr), lo, hi, L,
+                                 fill, o, cs);
+  }
+  finish(L, o, fill, cs);
+}
+
+unsigned grid_for(uint64_t work, uint64_t per_block, int per_cu) {
+  uint64_t g = (work + per_block - 1) / per_block;
+  const uint64_t cap = uint64_t(device_cu_count()) * per_cu;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g ? g : 1);
+}
+
+template <typename K, typename PB, typename PS>
+int hash_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
+  const uint64_t nslots = hash_slots(a.nR, a.plan.load_factor);
+  JoinCounters *c = ws.take<JoinCounters>(1);
+  Slot<K, PB> *slots = ws.take<Slot<K, PB>>(nslots);
+  *ctr = c;
+  if (!ws.base) return EIGER_OK;
+  hipStream_t s = a.s;
+  int rc;
+  if ((rc = fill_u64(reinterpret_cast<uint64_t *>(c), 4, 0, s))) return rc;
+  if (a.nR == 0 || a.nS == 0) return EIGER_OK;
+  if ((rc = fill_u32(reinterpret_cast<uint32_t *>(slots), nslots * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
+    return rc;
+  EIGER_LAUNCH("hash_build", (k_hash_build<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
+               static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1);
+  HashTab<K, PB> tab{slots, nslots - 1};
+  EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
+  EIGER_LAUNCH("hash_probe", (k_probe<HashTab<K, PB>, K, PS>),
+               dim3(grid_for(a.nS, uint64_t(kNT) * kIPT, 4)), dim3(kNT), 0, s, tab,
+               static_cast<const K *>(a.pk), static_cast<const PS *>(a.pp), a.nS, o);
+  return EIGER_OK;
+}
+
+}  // namespace
+
+uint64_t hash_slots(uint64_t n, float lf) {
+  if (!(lf > 0.f) || lf > 0.9f) lf = 0.5f;
+  uint64_t want = static_cast<uint64_t>(static_cast<double>(n) / lf) + 1;
+  uint64_t s = 64;
+  while (s < want) s <<= 1;
+  return s;
+}
+
+int run_global_hash(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
+  const bool k64 = a.kdt == EIGER_INT64, b64 = a.bpdt == EIGER_INT64, p64 = a.ppdt == EIGER_INT64;
+#define EIGER_DISPATCH(KT, BT, PT) return hash_impl<KT, BT, PT>(a, ws, ctr)
+  if (!k64 && !b64 && !p64) EIGER_DISPATCH(int32_t, int32_t, int32_t);
+  if (!k64 && !b64 && p64) EIGER_DISPATCH(int32_t, int32_t, int64_t);
+  if (!k64 && b64 && !p64) EIGER_DISPATCH(int32_t, int64_t, int32_t);
+  if (!k64 && b64 && p64) EIGER_DISPATCH(int32_t, int64_t, int64_t);
+  if (k64 && !b64 && !p64) EIGER_DISPATCH(int64_t, int32_t, int32_t);
+  if (k64 && !b64 && p64) EIGER_DISPATCH(int64_t, int32_t, int64_t);
+  if (k64 && b64 && !p64) EIGER_DISPATCH(int64_t, int64_t, int32_t);
+  EIGER_DISPATCH(int64_t, int64_t, int64_t);
+#undef EIGER_DISPATCH
+}
+
+}  // namespace eiger

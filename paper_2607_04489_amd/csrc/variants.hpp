@@ -1,0 +1,48 @@
+// variants.hpp -- interface between the ABI layer and the join variants.
+#pragma once
+
+#include "common.hpp"
+
+namespace eiger {
+
+struct JoinArgs {
+  const void *bk, *bp, *pk, *pp;  // build keys/payload, probe keys/payload (device)
+  uint64_t nR, nS;
+  int32_t kdt, bpdt, ppdt;        // eiger_dtype of keys, build payload, probe payload
+  eiger_plan_t plan;
+  uint32_t *ob, *op;              // outputs (device) or null in count-only mode
+  uint64_t cap;
+  hipStream_t s;
+};
+
+// Device words every variant leaves behind for the host to read.
+struct JoinCounters {
+  uint64_t count;     // pairs found (may exceed cap)
+  uint64_t checksum;  // sum of payload products mod 2^64
+  uint64_t flags;     // kFlag* bits
+  uint64_t pad;
+};
+
+constexpr uint64_t kFlagBuildOutOfRange = 1;  // DIRECT: a build key outside [build_min, build_max]
+
+// Each variant lays out its buffers in `ws` (sizing only when ws.base is null)
+// and, when not sizing, enqueues its kernels on a.s. `ctr` points into ws and
+// must be zeroed by the variant before use.
+int run_direct(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+int run_global_hash(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+
+// Largest key range the DIRECT variant accepts (its offset table is 4 B per key value).
+constexpr uint64_t kDirectMaxRange = uint64_t(1) << 30;
+
+// Slots of a global hash table for n build rows at load factor lf (power of two).
+uint64_t hash_slots(uint64_t n, float lf);
+
+// RADIX join configuration (LDS budget of the per-partition tables).
+struct RadixLimits {
+  uint32_t max_slots;   // LDS table slots for this key/payload width
+  uint32_t max_build;   // build rows one LDS table holds at load factor lf
+};
+RadixLimits radix_limits(int32_t kdt, int32_t bpdt, float lf);
+
+}  // namespace eiger
