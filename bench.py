@@ -1,0 +1,267 @@
+"""Benchmark of the adaptive equi-join hot path on one MI355X.
+
+One step = the whole path over one synthetic instance already resident in HBM:
+statistics of both key columns (min/max + HLL registers), the plan, and the
+join (build, probe, materialize the row-id pairs, payload aggregate).
+
+Default workload: the large sparse join -- build 16,777,216 unique int64 keys
+(full 64-bit range) with int64 payloads, probe 536,870,912 rows of which 90%
+carry a build key, int64 payloads. Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--selector rule|fixed_hash]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "probe tuples/s + HBM GB/s % peak; learned/batched vs fixed hash join"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name, device, scale=1):
+    import synth
+    if name == "sparse_unique64":
+        return synth.sparse_unique64(seed=42, n_build=(1 << 24) // scale, n_probe=(1 << 29) // scale,
+                                     device=device)
+    if name == "plain_dense":
+        return synth.plain_dense(seed=42, device=device)
+    if name.startswith("skewed_dup32"):
+        s = float(name.split("_s")[-1]) if "_s" in name else 1.0
+        return synth.skewed_dup32(seed=42, n_distinct=(1 << 24) // scale, n_probe=(1 << 28) // scale,
+                                  zipf_s=s, device=device)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(name, inp):
+    if name == "sparse_unique64":
+        return (f"large sparse join: build {inp.n_build:,} unique int64 keys over the full 64-bit range "
+                f"+ int64 payload; probe {inp.n_probe:,} rows, 90% keys drawn from the build keys, "
+                f"10% absent; int64 payloads")
+    if name == "plain_dense":
+        return (f"plain join: build {inp.n_build:,} int32 keys = shuffled [0,65536), probe {inp.n_probe:,} "
+                f"int32 keys U[0,81920), int32 payloads")
+    return (f"skewed many-to-many join: build {inp.n_build:,} int32 rows over {inp.meta['n_distinct']:,} "
+            f"distinct keys (geometric duplicates, mean 4), probe {inp.n_probe:,} Zipf(s={inp.meta['zipf_s']})")
+
+
+def esize(t):
+    return t.element_size()
+
+
+def kernel_bytes(plan, inp, count):
+    """Algorithmic bytes per step of each kernel: every input element the
+    kernel's definition consumes is read once, every output element written once."""
+    import paper_2607_04489_amd as eg
+    nR, nS = inp.n_build, inp.n_probe
+    K, PB, PS = esize(inp.build_keys), esize(inp.build_payload), esize(inp.probe_payload)
+    b = {"stats_partial": (nR + nS) * K}
+    if plan.variant == eg.DIRECT:
+        b["direct_count"] = nR * K
+        b["direct_fill"] = nR * (K + PB) + nR * (4 + PB)
+        b["direct_probe"] = nS * (K + PS) + count * 8
+    elif plan.variant == eg.GLOBAL_HASH:
+        b["hash_build"] = nR * (K + PB)
+        b["hash_probe"] = nS * (K + PS) + count * 8
+    else:
+        passes = 2 if plan.radix_bits > 9 else (1 if plan.radix_bits < 2 else plan.radix_passes)
+        b["radix_hist"] = passes * (nR + nS) * K
+        sc = (nR * (K + PB) + nS * (K + PS)) + (nR * (K + PB + 4) + nS * (K + PS + 4))
+        if passes == 2:
+            sc += 2 * (nR * (K + PB + 4) + nS * (K + PS + 4))
+        b["radix_scatter"] = sc
+        b["radix_join"] = nR * (K + PB + 4) + nS * (K + PS + 4) + count * 8
+    return b
+
+
+def cpu_baseline(name):
+    """The oracle, untuned, on a 1/32-scale instance of the same workload (same
+    generator and distributions), single-threaded: statistics of both sides and
+    the sort-merge join with canonical pairs."""
+    import oracle
+    scale = 32 if name in ("sparse_unique64",) or name.startswith("skewed") else 1
+    inp = make_workload(name, "cpu", scale=scale)
+    t0 = time.perf_counter()
+    oracle.column_stats(inp.build_keys)
+    oracle.column_stats(inp.probe_keys)
+    _, cnt, _ = oracle.join_sortmerge(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload)
+    dt = time.perf_counter() - t0
+    return {"value": inp.n_probe / dt, "unit": "probe tuples/s", "cores": 1, "kind": "oracle",
+            "sample": (f"1/{scale}-scale instance of the same generator: build {inp.n_build:,}, probe "
+                       f"{inp.n_probe:,} rows ({cnt:,} pairs); stats of both sides + sort-merge join "
+                       f"with canonical pairs; {dt:.1f} s on one host core")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sparse_unique64")
+    ap.add_argument("--selector", default="rule", choices=["rule", "fixed_hash"])
+    ap.add_argument("--force", default="", help="variant,bits,passes,lf (e.g. radix,14,2,0.5)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the fixed-hash comparison run")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2607_04489_amd as eg
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
+
+    if not eg.available():
+        import __graft_entry__
+        __graft_entry__.build()
+    dev = torch.device("cuda:0")
+    log(f"generating {args.workload} on {dev}")
+    inp = make_workload(args.workload, dev)
+    torch.cuda.synchronize()
+
+    sel = {"rule": eg.SEL_RULE, "fixed_hash": eg.SEL_FIXED_HASH}[args.selector]
+    forced = None
+    if args.force:
+        v, bits, passes, lf = args.force.split(",")
+        forced = eg.make_plan({"direct": eg.DIRECT, "hash": eg.GLOBAL_HASH, "radix": eg.RADIX}[v],
+                              int(bits), int(passes), float(lf))
+        sel = eg.SEL_FORCED
+
+    # buffers allocated once, outside the timed region
+    sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
+    plan = eg.join_plan(sb, sp, sel, forced)
+    ws_stats = torch.empty(max(eg.lib().eiger_stats_workspace_size(inp.n_probe, eg.column(inp.probe_keys).dtype),
+                               eg.lib().eiger_stats_workspace_size(inp.n_build, eg.column(inp.build_keys).dtype)),
+                           dtype=torch.uint8, device=dev)
+
+    def prepare(p):
+        need = eg.join_workspace_size(p, inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload)
+        cap = max(int(p.predicted_out * 1.25) + 1024, inp.n_probe)
+        return (torch.empty(need, dtype=torch.uint8, device=dev),
+                (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev)))
+
+    ws_join, outs = prepare(plan)
+
+    def step(selector, forced_plan):
+        b = eg.stats(inp.build_keys, workspace=ws_stats)
+        p = eg.stats(inp.probe_keys, workspace=ws_stats)
+        pl = eg.join_plan(b, p, selector, forced_plan)
+        return pl, eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, pl,
+                           workspace=ws_join, outputs=outs)
+
+    log(f"plan {plan.describe()}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        pl, res = step(sel, forced)
+    torch.cuda.synchronize()
+
+    eg.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        pl, res = step(sel, forced)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = eg.profile_read()
+    eg.profile_enable(False)
+    ms = dt / args.steps * 1e3
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step, count={res.count}")
+
+    # sanity against the generator's record (no oracle in the timed path)
+    verified = None
+    if args.workload == "sparse_unique64":
+        src = inp.meta["source_row"]
+        hit = src >= 0
+        expect_cnt = int(hit.sum())
+        expect_cs = int((inp.build_payload[src[hit]] * inp.probe_payload[hit]).sum())
+        verified = (res.count == expect_cnt and res.checksum == expect_cs)
+
+    kb = kernel_bytes(pl, inp, res.count)
+    rows = []
+    for name, (launches, total_ms) in prof.items():
+        per_step_ms = total_ms / args.steps
+        alg = kb.get(name)
+        rows.append((per_step_ms, name, launches // args.steps, alg))
+    rows.sort(reverse=True)
+    for per_step_ms, name, l, alg in rows:
+        gbs = (alg / (per_step_ms * 1e-3) / 1e9) if alg else None
+        log(f"  {name:16s} {per_step_ms:8.3f} ms/step  launches/step={l}  "
+            + (f"alg {alg/1e9:.3f} GB -> {gbs:.0f} GB/s" if alg else ""))
+    dom_ms, dom, dom_launches, dom_bytes = rows[0]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_bytes else None
+    step_alg = sum(kb.values())
+
+    compare = None
+    if not args.no_compare and sel != eg.SEL_FIXED_HASH:
+        fplan = eg.join_plan(sb, sp, eg.SEL_FIXED_HASH)
+        ws_join, outs = prepare(fplan)
+        for _ in range(max(1, args.warmup)):
+            step(eg.SEL_FIXED_HASH, None)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, r2 = step(eg.SEL_FIXED_HASH, None)
+        torch.cuda.synchronize()
+        fms = (time.perf_counter() - t1) / args.steps * 1e3
+        assert (r2.count, r2.checksum) == (res.count, res.checksum)
+        compare = {"fixed_hash_ms_per_step": round(fms, 4), "speedup_vs_fixed_hash": round(fms / ms, 3)}
+        log(f"fixed hash join: {fms:.3f} ms/step")
+
+    out = {
+        "metric": METRIC,
+        "value": inp.n_probe / (ms * 1e-3),
+        "unit": "probe tuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64" if inp.build_keys.dtype == torch.int64 else "int32",
+        "data": "synthetic (seeded counter-based generator, resident in HBM)",
+        "config": {"workload": describe(args.workload, inp), "name": args.workload,
+                   "n_build": inp.n_build, "n_probe": inp.n_probe, "pairs": res.count,
+                   "plan": pl.describe(), "selector": args.selector if not args.force else "forced"},
+        "effective_GBps": round(step_alg / (ms * 1e-3) / 1e9, 1),
+        "effective_frac_of_peak": round(step_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "verified_vs_generator": verified,
+        "kernels_ms_per_step": {n: round(t, 4) for t, n, _, _ in rows},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": None,
+                     "alg_bytes_per_launch": int(dom_bytes / max(dom_launches, 1)) if dom_bytes else None,
+                     "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 5)},
+    }
+    if compare:
+        out["vs_fixed_hash"] = compare
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
