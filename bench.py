@@ -73,8 +73,13 @@ def kernel_bytes(plan, inp, count):
     elif plan.variant == eg.GLOBAL_HASH:
         b["hash_build"] = nR * (K + PB)
         b["hash_probe"] = nS * (K + PS) + count * 8
+    elif plan.variant == eg.RADIX_CACHE:
+        b["radix_hist"] = (nR + nS) * K
+        b["radix_scatter"] = nS * (K + PS) + nS * (K + PS + 4)
+        b["cache_build"] = nR * (K + PB)
+        b["cache_probe"] = nS * (K + PS + 4) + count * 8
     else:
-        passes = 2 if plan.radix_bits > 9 else (1 if plan.radix_bits < 2 else plan.radix_passes)
+        passes = 2 if plan.radix_bits > 10 else (1 if plan.radix_bits < 2 else plan.radix_passes)
         b["radix_hist"] = passes * (nR + nS) * K
         sc = (nR * (K + PB) + nS * (K + PS)) + (nR * (K + PB + 4) + nS * (K + PS + 4))
         if passes == 2:
@@ -145,7 +150,8 @@ def main():
     forced = None
     if args.force:
         v, bits, passes, lf = args.force.split(",")
-        forced = eg.make_plan({"direct": eg.DIRECT, "hash": eg.GLOBAL_HASH, "radix": eg.RADIX}[v],
+        forced = eg.make_plan({"direct": eg.DIRECT, "hash": eg.GLOBAL_HASH, "radix": eg.RADIX,
+                               "cache": eg.RADIX_CACHE}[v],
                               int(bits), int(passes), float(lf))
         sel = eg.SEL_FORCED
 

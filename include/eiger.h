@@ -85,7 +85,9 @@ typedef struct {
 typedef enum {
     EIGER_DIRECT = 0,      /* table indexed by key - min; needs a dense build key range */
     EIGER_GLOBAL_HASH = 1, /* one open-addressing table in HBM (non-partitioned hash join) */
-    EIGER_RADIX = 2        /* hash-radix partitioning, then LDS-resident tables per partition */
+    EIGER_RADIX = 2,       /* hash-radix partitioning, then LDS-resident tables per partition */
+    EIGER_RADIX_CACHE = 3  /* one partitioning pass of the probe side; one partition-major table in
+                              HBM whose per-partition regions are read from one XCD's L2 at a time */
 } eiger_variant;
 
 typedef enum {
@@ -99,9 +101,10 @@ typedef enum {
  * A join plan. eiger_join_plan fills it; callers may also build one by hand
  * through EIGER_SEL_FORCED. Fields:
  *  variant      eiger_variant
- *  radix_bits   RADIX: total partition bits (fan-out 2^radix_bits), 1..18
- *  radix_passes RADIX: 1 or 2 partitioning passes over each side
- *  load_factor  GLOBAL_HASH / RADIX: target occupancy of a table, (0, 0.9]
+ *  radix_bits   RADIX: total partition bits (fan-out 2^radix_bits), 1..18;
+ *               RADIX_CACHE: partition bits of its single pass, 1..10
+ *  radix_passes RADIX: 1 or 2 partitioning passes over each side (ignored by RADIX_CACHE)
+ *  load_factor  GLOBAL_HASH / RADIX / RADIX_CACHE: target occupancy of a table, (0, 0.9]
  *  key_dtype    dtype of both key columns
  *  build_min/max  DIRECT: range of the build keys (from the build statistics)
  *  predicted_out  estimated result size |R||S| / max(ndv_R, ndv_S) (informational)

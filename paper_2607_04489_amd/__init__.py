@@ -31,8 +31,8 @@ EIGER_ERR_UNSUPPORTED = -7
 EIGER_ERR_MODEL = -8
 
 INT32, INT64 = 0, 1
-DIRECT, GLOBAL_HASH, RADIX = 0, 1, 2
-VARIANT_NAMES = {DIRECT: "direct", GLOBAL_HASH: "global_hash", RADIX: "radix"}
+DIRECT, GLOBAL_HASH, RADIX, RADIX_CACHE = 0, 1, 2, 3
+VARIANT_NAMES = {DIRECT: "direct", GLOBAL_HASH: "global_hash", RADIX: "radix", RADIX_CACHE: "radix_cache"}
 SEL_RULE, SEL_LEARNED, SEL_FIXED_HASH, SEL_FORCED = 0, 1, 2, 3
 HLL_P = 14
 
@@ -67,8 +67,9 @@ class PlanT(ctypes.Structure):
              "predicted_out": int(self.predicted_out)}
         if self.variant != DIRECT:
             d["load_factor"] = round(float(self.load_factor), 3)
-        if self.variant == RADIX:
+        if self.variant in (RADIX, RADIX_CACHE):
             d["radix_bits"] = int(self.radix_bits)
+        if self.variant == RADIX:
             d["radix_passes"] = int(self.radix_passes)
         return d
 

@@ -135,7 +135,7 @@ int check_join_inputs(const eiger_column &bk, const eiger_column &bp, const eige
   if (bk.n != bp.n) return fail(EIGER_ERR_INVALID_ARG, "build_payload has a different row count than build_keys");
   if (pk.n != pp.n) return fail(EIGER_ERR_INVALID_ARG, "probe_payload has a different row count than probe_keys");
   if (!plan) return fail(EIGER_ERR_INVALID_ARG, "plan is NULL");
-  if (plan->variant < EIGER_DIRECT || plan->variant > EIGER_RADIX)
+  if (plan->variant < EIGER_DIRECT || plan->variant > EIGER_RADIX_CACHE)
     return fail(EIGER_ERR_INVALID_ARG, "plan.variant is not an eiger_variant");
   if (plan->key_dtype != bk.dtype) return fail(EIGER_ERR_DTYPE, "plan.key_dtype differs from the key columns");
   if (plan->variant == EIGER_DIRECT && bk.n > 0) {
@@ -153,6 +153,8 @@ int check_join_inputs(const eiger_column &bk, const eiger_column &bp, const eige
     if (plan->radix_passes < 1 || plan->radix_passes > 2)
       return fail(EIGER_ERR_INVALID_ARG, "plan.radix_passes must be 1 or 2");
   }
+  if (plan->variant == EIGER_RADIX_CACHE && (plan->radix_bits < 1 || plan->radix_bits > kCacheMaxBits))
+    return fail(EIGER_ERR_INVALID_ARG, "RADIX_CACHE plan.radix_bits must be in [1, 10]");
   return EIGER_OK;
 }
 
@@ -181,18 +183,30 @@ int run_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   switch (a.plan.variant) {
     case EIGER_DIRECT: return run_direct(a, ws, ctr);
     case EIGER_GLOBAL_HASH: return run_global_hash(a, ws, ctr);
-    default: return run_radix(a, ws, ctr);
+    case EIGER_RADIX: return run_radix(a, ws, ctr);
+    default: return run_radix_cache(a, ws, ctr);
   }
 }
 
 // ------------------------------------------------------------------ planning
 
-constexpr double kHashTableBudget = 64.0 * 1024 * 1024;  // bytes a GLOBAL_HASH table may take
+constexpr double kHashTableBudget = 4.0 * 1024 * 1024 * 1024;  // bytes a GLOBAL_HASH table may take
 
 uint64_t key_range(const eiger_stats_t &s) {
   if (s.n == 0) return 0;
   const uint64_t r = static_cast<uint64_t>(s.max) - static_cast<uint64_t>(s.min) + 1;
   return r == 0 ? UINT64_MAX : r;  // the whole 64-bit domain saturates
+}
+
+constexpr double kCacheRegionBudget = 1.5 * 1024 * 1024;  // bytes of one RADIX_CACHE table region
+
+// Partition bits that bring one RADIX_CACHE table region under the L2 budget
+// (8-byte build payloads assumed: the statistics do not carry payload widths).
+int cache_bits_for(uint64_t n_build, int32_t kdt, float lf) {
+  const double bytes = static_cast<double>(n_build) / lf * static_cast<double>(slot_bytes(kdt, EIGER_INT64));
+  int bits = 1;
+  while (bits < kCacheMaxBits && bytes / std::ldexp(1.0, bits) > kCacheRegionBudget) ++bits;
+  return bits;
 }
 
 int radix_bits_for(uint64_t n_build, int32_t kdt, int32_t bpdt, float lf) {
@@ -227,6 +241,16 @@ void rule_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out
   if (table <= kHashTableBudget) {
     out->variant = EIGER_GLOBAL_HASH;
     out->load_factor = lf;
+    return;
+  }
+  // Large probes: one pass over the probe side with L2-sized table regions
+  // when a region fits at <= 2^10 partitions; otherwise LDS tables.
+  const double region = table / std::ldexp(1.0, kCacheMaxBits);
+  if (region <= kCacheRegionBudget) {
+    out->variant = EIGER_RADIX_CACHE;
+    out->load_factor = lf;
+    out->radix_bits = cache_bits_for(static_cast<uint64_t>(b.n), b.dtype, lf);
+    out->radix_passes = 1;
     return;
   }
   out->variant = EIGER_RADIX;
@@ -286,7 +310,7 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
       break;
     case EIGER_SEL_FORCED:
       if (!forced) return fail(EIGER_ERR_INVALID_ARG, "eiger_join_plan: EIGER_SEL_FORCED needs `forced`");
-      if (forced->variant < EIGER_DIRECT || forced->variant > EIGER_RADIX)
+      if (forced->variant < EIGER_DIRECT || forced->variant > EIGER_RADIX_CACHE)
         return fail(EIGER_ERR_INVALID_ARG, "eiger_join_plan: forced.variant is not an eiger_variant");
       p.variant = forced->variant;
       p.load_factor = forced->load_factor;
@@ -297,6 +321,11 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
         if (p.radix_bits < 1 || p.radix_bits > 18)
           p.radix_bits = radix_bits_for(static_cast<uint64_t>(build->n), build->dtype, EIGER_INT64, p.load_factor);
         if (p.radix_passes < 1 || p.radix_passes > 2) p.radix_passes = p.radix_bits > 8 ? 2 : 1;
+      }
+      if (p.variant == EIGER_RADIX_CACHE) {
+        if (p.radix_bits < 1 || p.radix_bits > kCacheMaxBits)
+          p.radix_bits = cache_bits_for(static_cast<uint64_t>(build->n), build->dtype, p.load_factor);
+        p.radix_passes = 1;
       }
       if (p.variant == EIGER_DIRECT && build->n > 0 && key_range(*build) > kDirectMaxRange)
         return fail(EIGER_ERR_UNSUPPORTED, "eiger_join_plan: DIRECT over a key range above 2^30 values");

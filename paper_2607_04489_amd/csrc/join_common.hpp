@@ -13,6 +13,16 @@
 
 namespace eiger {
 
+// Slot of a hash table in device memory: key, build row id and build payload
+// side by side, 16 bytes (32 when key and payload are both 8 bytes), so one
+// probe step is one aligned vector load. rowid == kEmpty marks an empty slot.
+template <typename K, typename P>
+struct alignas((sizeof(K) + sizeof(P) + 4 <= 16) ? 16 : 32) Slot {
+  K key;
+  uint32_t rowid;
+  P pay;
+};
+
 // Where pairs go. ob/op may be null (count-only); positions >= cap are dropped.
 struct EmitOut {
   uint32_t *ob;
@@ -60,55 +70,156 @@ __device__ __forceinline__ void flush(EmitLds<NT, SCAP> &L, const EmitOut &o, ui
   __syncthreads();
 }
 
-// Finish a workgroup's share: flush the stage and add its checksum part.
+// Finish a workgroup's share: flush the stage and add its checksum part. In
+// count-only mode `fill` is instead the workgroup's whole pair count (uniform).
 template <int NT, int SCAP>
-__device__ __forceinline__ void finish(EmitLds<NT, SCAP> &L, const EmitOut &o, uint32_t fill,
+__device__ __forceinline__ void finish(EmitLds<NT, SCAP> &L, const EmitOut &o, uint64_t fill,
                                        uint64_t cs) {
-  flush(L, o, fill);
+  if (o.ob) {
+    flush(L, o, static_cast<uint32_t>(fill));
+  } else if (threadIdx.x == 0 && fill) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(o.cursor), static_cast<unsigned long long>(fill));
+  }
   const uint64_t s = block_sum_u64<NT>(cs, L.red);
   if (threadIdx.x == 0 && s != 0)
     atomicAdd(reinterpret_cast<unsigned long long *>(o.checksum), static_cast<unsigned long long>(s));
 }
 
-// Probe rows [lo, hi) (at most NT * IPT of them) against `tab` and materialize
-// the matches. Tab provides
-//   uint32_t lookup(K key, uint32_t &first_rowid, uint64_t &payload_sum) const
-//   template <class F> void for_each(K key, F f) const   // f(build_rowid)
-// Probe row ids are `prow[i]` when prow is non-null, else the index i itself.
-// Uniform across the workgroup (contains barriers).
-template <int NT, int IPT, int SCAP, class Tab, typename K, typename PS>
-__device__ __forceinline__ void probe_tile(const Tab &tab, const K *__restrict__ pk,
+// Registers of one probe sub-tile: up to IPT rows per thread, rows
+// lo + k * NT + threadIdx.x. Loading the next sub-tile before processing the
+// current one keeps global loads in flight across the LDS barriers (on gfx950
+// a barrier waits for LDS traffic only).
+template <int IPT, typename K, typename PS>
+struct ProbeRegs {
+  K key[IPT];
+  PS pay[IPT];
+  uint32_t rid[IPT];
+  uint64_t lo, hi;
+};
+
+template <int NT, int IPT, typename K, typename PS>
+__device__ __forceinline__ void probe_load(ProbeRegs<IPT, K, PS> &r, const K *__restrict__ pk,
                                            const PS *__restrict__ pp,
                                            const uint32_t *__restrict__ prow, uint64_t lo,
-                                           uint64_t hi, EmitLds<NT, SCAP> &L, uint32_t &fill,
-                                           const EmitOut &o, uint64_t &cs) {
-  K key[IPT];
-  uint32_t cnt[IPT], first[IPT], rid[IPT];
+                                           uint64_t hi) {
+  r.lo = lo;
+  r.hi = hi;
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const uint64_t i = lo + uint64_t(k) * NT + threadIdx.x;
+    if (i < hi) {
+      r.key[k] = pk[i];
+      r.pay[k] = pp[i];
+      r.rid[k] = prow ? prow[i] : static_cast<uint32_t>(i);
+    }
+  }
+}
+
+// Count the matches of every loaded row. Tables of two kinds:
+//  * hashed tables (Tab::kHashed) expose home(key), next(i), load(i) -> slot
+//    and a `unique` flag (build keys known to be distinct). The first slot of
+//    every row is loaded before any is inspected, so a thread keeps IPT random
+//    loads in flight; only rows whose walk is not finished load again, and a
+//    unique table stops a walk at its first match.
+//  * other tables expose lookup(key, first_rowid, payload_sum) -> count.
+template <int NT, int IPT, class Tab, typename K, typename PS>
+__device__ __forceinline__ void count_matches(const Tab &tab, const ProbeRegs<IPT, K, PS> &r,
+                                              uint32_t (&cnt)[IPT], uint32_t (&first)[IPT],
+                                              uint64_t (&psum)[IPT]) {
+  bool valid[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    valid[k] = r.lo + uint64_t(k) * NT + threadIdx.x < r.hi;
+    cnt[k] = 0;
+    psum[k] = 0;
+  }
+  if constexpr (Tab::kHashed) {
+    uint32_t idx[IPT];
+    typename Tab::SlotT sl[IPT];
+    bool live[IPT];
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+      if (valid[k]) idx[k] = tab.home(r.key[k]);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+      if (valid[k]) sl[k] = tab.load(idx[k]);
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      live[k] = valid[k];
+      if (!live[k]) continue;
+      if (sl[k].rowid == kEmpty) {
+        live[k] = false;
+      } else {
+        if (sl[k].key == r.key[k]) {
+          ++cnt[k];
+          first[k] = sl[k].rowid;
+          psum[k] += static_cast<uint64_t>(sext(sl[k].pay));
+          if (tab.unique) live[k] = false;
+        }
+        if (live[k]) {
+          idx[k] = tab.next(idx[k]);
+          any = true;
+        }
+      }
+    }
+    while (any) {
+      any = false;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k)
+        if (live[k]) sl[k] = tab.load(idx[k]);
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        if (!live[k]) continue;
+        if (sl[k].rowid == kEmpty) {
+          live[k] = false;
+        } else {
+          if (sl[k].key == r.key[k]) {
+            ++cnt[k];
+            first[k] = sl[k].rowid;
+            psum[k] += static_cast<uint64_t>(sext(sl[k].pay));
+            if (tab.unique) live[k] = false;
+          }
+          if (live[k]) {
+            idx[k] = tab.next(idx[k]);
+            any = true;
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+      if (valid[k]) cnt[k] = tab.lookup(r.key[k], first[k], psum[k]);
+  }
+}
+
+// Probe the loaded rows against `tab` and materialize the matches. Tables also
+// provide  template <class F> void for_each(K key, F f) const  (f(build_rowid)
+// for every match) for rows with more than one match.
+// Uniform across the workgroup (contains barriers).
+template <int NT, int IPT, int SCAP, class Tab, typename K, typename PS>
+__device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IPT, K, PS> &r,
+                                              EmitLds<NT, SCAP> &L, uint64_t &fill,
+                                              const EmitOut &o, uint64_t &cs) {
+  uint32_t cnt[IPT], first[IPT];
+  uint64_t psum[IPT];
+  count_matches<NT, IPT>(tab, r, cnt, first, psum);
   uint32_t mine = 0;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
-    const uint64_t i = lo + uint64_t(k) * NT + threadIdx.x;
-    cnt[k] = 0;
-    if (i < hi) {
-      key[k] = pk[i];
-      rid[k] = prow ? prow[i] : static_cast<uint32_t>(i);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    const uint64_t i = lo + uint64_t(k) * NT + threadIdx.x;
-    if (i < hi) {
-      uint64_t psum = 0;
-      cnt[k] = tab.lookup(key[k], first[k], psum);
-      if (cnt[k]) cs += psum * static_cast<uint64_t>(sext(pp[i]));
-      mine += cnt[k];
-    }
+    if (cnt[k]) cs += psum[k] * static_cast<uint64_t>(sext(r.pay[k]));
+    mine += cnt[k];
   }
   uint32_t total;
   const uint32_t off = block_exclusive_scan<NT>(mine, L.scan, &total);
   if (total == 0) return;
+  if (!o.ob) {  // count-only: no positions are needed, so nothing is reserved
+    fill += total;
+    return;
+  }
   if (fill + total > SCAP) {
-    flush(L, o, fill);
+    flush(L, o, static_cast<uint32_t>(fill));
     fill = 0;
   }
   if (total > SCAP) {
@@ -119,32 +230,52 @@ __device__ __forceinline__ void probe_tile(const Tab &tab, const K *__restrict__
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       if (cnt[k] == 1) {
-        put_pair(o, pos++, first[k], rid[k]);
+        put_pair(o, pos++, first[k], r.rid[k]);
       } else if (cnt[k] > 1) {
-        const uint32_t r = rid[k];
-        tab.for_each(key[k], [&](uint32_t b) { put_pair(o, pos++, b, r); });
+        const uint32_t rr = r.rid[k];
+        tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
       }
     }
     return;
   }
-  uint32_t pos = fill + off;
+  uint32_t pos = static_cast<uint32_t>(fill) + off;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     if (cnt[k] == 1) {
       L.b[pos] = first[k];
-      L.p[pos] = rid[k];
+      L.p[pos] = r.rid[k];
       ++pos;
     } else if (cnt[k] > 1) {
-      const uint32_t r = rid[k];
-      tab.for_each(key[k], [&](uint32_t b) {
+      const uint32_t rr = r.rid[k];
+      tab.for_each(r.key[k], [&](uint32_t b) {
         L.b[pos] = b;
-        L.p[pos] = r;
+        L.p[pos] = rr;
         ++pos;
       });
     }
   }
   __syncthreads();
   fill += total;
+}
+
+// Probe the rows [lo, hi) in sub-tiles of NT * IPT rows, prefetching each next
+// sub-tile while the current one is processed. Uniform across the workgroup.
+template <int NT, int IPT, int SCAP, class Tab, typename K, typename PS>
+__device__ __forceinline__ void probe_range(const Tab &tab, const K *__restrict__ pk,
+                                            const PS *__restrict__ pp,
+                                            const uint32_t *__restrict__ prow, uint64_t lo,
+                                            uint64_t hi, EmitLds<NT, SCAP> &L, uint64_t &fill,
+                                            const EmitOut &o, uint64_t &cs) {
+  constexpr uint64_t sub = uint64_t(NT) * IPT;
+  if (lo >= hi) return;
+  ProbeRegs<IPT, K, PS> cur, nxt;
+  probe_load<NT, IPT>(cur, pk, pp, prow, lo, lo + sub < hi ? lo + sub : hi);
+  for (uint64_t t = lo; t < hi; t += sub) {
+    const uint64_t n0 = t + sub;
+    if (n0 < hi) probe_load<NT, IPT>(nxt, pk, pp, prow, n0, n0 + sub < hi ? n0 + sub : hi);
+    probe_process<NT, IPT, SCAP>(tab, cur, L, fill, o, cs);
+    cur = nxt;
+  }
 }
 
 }  // namespace eiger

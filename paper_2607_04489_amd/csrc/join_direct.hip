@@ -18,6 +18,7 @@ constexpr int kSCAP = 4096;
 
 template <typename K, typename PB>
 struct DirectTab {
+  static constexpr bool kHashed = false;
   uint64_t min;  // as two's-complement bits
   uint64_t range;
   const uint32_t *__restrict__ end;  // end offset of each key value's run
@@ -74,20 +75,21 @@ __global__ void k_direct_fill(const K *__restrict__ keys, const PB *__restrict__
   }
 }
 
+// Each workgroup streams a contiguous range of probe rows (an equal share of
+// whole sub-tiles), so its prefetch of the next sub-tile is always useful.
 template <class Tab, typename K, typename PS>
 __global__ void __launch_bounds__(kNT) k_probe(Tab tab, const K *__restrict__ pk,
                                                const PS *__restrict__ pp, uint64_t n, EmitOut o) {
   __shared__ EmitLds<kNT, kSCAP> L;
-  uint32_t fill = 0;
+  uint64_t fill = 0;
   uint64_t cs = 0;
-  constexpr uint64_t tile = uint64_t(kNT) * kIPT;
-  const uint64_t ntiles = (n + tile - 1) / tile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t lo = t * tile;
-    const uint64_t hi = lo + tile < n ? lo + tile : n;
-    probe_tile<kNT, kIPT, kSCAP>(tab, pk, pp, static_cast<const uint32_t *>(nullptr), lo, hi, L,
-                                 fill, o, cs);
-  }
+  constexpr uint64_t sub = uint64_t(kNT) * kIPT;
+  const uint64_t nsub = (n + sub - 1) / sub;
+  const uint64_t per = (nsub + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = blockIdx.x * per * sub;
+  const uint64_t hi = lo + per * sub < n ? lo + per * sub : n;
+  probe_range<kNT, kIPT, kSCAP>(tab, pk, pp, static_cast<const uint32_t *>(nullptr), lo, hi, L, fill,
+                                o, cs);
   finish(L, o, fill, cs);
 }
 

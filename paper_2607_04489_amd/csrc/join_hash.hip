@@ -20,44 +20,48 @@ constexpr int kNT = 256;
 constexpr int kIPT = 8;
 constexpr int kSCAP = 4096;
 
-template <typename K, typename P>
-struct alignas((sizeof(K) + sizeof(P) + 4 <= 16) ? 16 : 32) Slot {
-  K key;
-  uint32_t rowid;
-  P pay;
-};
-
 template <typename K, typename PB>
 struct HashTab {
+  static constexpr bool kHashed = true;
+  using SlotT = Slot<K, PB>;
   const Slot<K, PB> *__restrict__ slots;
   uint64_t mask;
+  const uint32_t *dup;  // device flag: nonzero when some build key occurs twice
+  bool unique;          // set in the kernel from *dup
 
-  __device__ __forceinline__ uint32_t lookup(K key, uint32_t &first, uint64_t &psum) const {
-    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
-    uint32_t c = 0;
-    for (;;) {
-      const Slot<K, PB> s = slots[i];
-      if (s.rowid == kEmpty) break;
-      if (s.key == key) {
-        first = s.rowid;
-        psum += static_cast<uint64_t>(sext(s.pay));
-        ++c;
-      }
-      i = (i + 1) & mask;
-    }
-    return c;
+  __device__ __forceinline__ void init() { unique = dup && *dup == 0; }
+  __device__ __forceinline__ uint32_t home(K key) const {
+    return static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) & mask);
   }
+  __device__ __forceinline__ uint32_t next(uint32_t i) const { return static_cast<uint32_t>((i + 1) & mask); }
+  __device__ __forceinline__ SlotT load(uint32_t i) const { return slots[i]; }
   template <class F>
   __device__ __forceinline__ void for_each(K key, F f) const {
-    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
+    uint32_t i = home(key);
     for (;;) {
       const Slot<K, PB> s = slots[i];
       if (s.rowid == kEmpty) break;
       if (s.key == key) f(s.rowid);
-      i = (i + 1) & mask;
+      i = next(i);
     }
   }
 };
+
+// Sets *dup when some build key occurs more than once: every build row walks
+// its key's cluster and counts equal keys. Afterwards probes of a table with
+// distinct keys stop at their first match.
+template <typename K, typename PB>
+__global__ void k_hash_unique(const K *__restrict__ keys, uint64_t n, HashTab<K, PB> tab,
+                              uint32_t *dup) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+    if (*static_cast<volatile uint32_t *>(dup)) return;
+    const K key = keys[r];
+    uint32_t c = 0;
+    tab.for_each(key, [&](uint32_t) { ++c; });
+    if (c > 1) atomicOr(dup, 1u);
+  }
+}
 
 template <typename K, typename PB>
 __global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ pay, uint64_t n,
@@ -78,20 +82,22 @@ __global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ 
   }
 }
 
+// Each workgroup streams a contiguous range of probe rows (an equal share of
+// whole sub-tiles), so its prefetch of the next sub-tile is always useful.
 template <class Tab, typename K, typename PS>
 __global__ void __launch_bounds__(kNT) k_probe(Tab tab, const K *__restrict__ pk,
                                                const PS *__restrict__ pp, uint64_t n, EmitOut o) {
   __shared__ EmitLds<kNT, kSCAP> L;
-  uint32_t fill = 0;
+  uint64_t fill = 0;
   uint64_t cs = 0;
-  constexpr uint64_t tile = uint64_t(kNT) * kIPT;
-  const uint64_t ntiles = (n + tile - 1) / tile;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint64_t lo = t * tile;
-    const uint64_t hi = lo + tile < n ? lo + tile : n;
-    probe_tile<kNT, kIPT, kSCAP>(tab, pk, pp, static_cast<const uint32_t *>(nullptr), lo, hi, L,
-                                 fill, o, cs);
-  }
+  tab.init();
+  constexpr uint64_t sub = uint64_t(kNT) * kIPT;
+  const uint64_t nsub = (n + sub - 1) / sub;
+  const uint64_t per = (nsub + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = blockIdx.x * per * sub;
+  const uint64_t hi = lo + per * sub < n ? lo + per * sub : n;
+  probe_range<kNT, kIPT, kSCAP>(tab, pk, pp, static_cast<const uint32_t *>(nullptr), lo, hi, L, fill,
+                                o, cs);
   finish(L, o, fill, cs);
 }
 
@@ -106,6 +112,7 @@ template <typename K, typename PB, typename PS>
 int hash_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   const uint64_t nslots = hash_slots(a.nR, a.plan.load_factor);
   JoinCounters *c = ws.take<JoinCounters>(1);
+  uint32_t *dup = ws.take<uint32_t>(1);
   Slot<K, PB> *slots = ws.take<Slot<K, PB>>(nslots);
   *ctr = c;
   if (!ws.base) return EIGER_OK;
@@ -113,11 +120,14 @@ int hash_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   int rc;
   if ((rc = fill_u64(reinterpret_cast<uint64_t *>(c), 4, 0, s))) return rc;
   if (a.nR == 0 || a.nS == 0) return EIGER_OK;
+  if ((rc = fill_u32(dup, 1, 0, s))) return rc;
   if ((rc = fill_u32(reinterpret_cast<uint32_t *>(slots), nslots * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
     return rc;
   EIGER_LAUNCH("hash_build", (k_hash_build<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
                static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1);
-  HashTab<K, PB> tab{slots, nslots - 1};
+  HashTab<K, PB> tab{slots, nslots - 1, dup, false};
+  EIGER_LAUNCH("hash_unique", (k_hash_unique<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
+               static_cast<const K *>(a.bk), a.nR, tab, dup);
   EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
   EIGER_LAUNCH("hash_probe", (k_probe<HashTab<K, PB>, K, PS>),
                dim3(grid_for(a.nS, uint64_t(kNT) * kIPT, 4)), dim3(kNT), 0, s, tab,

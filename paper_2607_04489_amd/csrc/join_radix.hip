@@ -31,7 +31,9 @@ constexpr int kPNT = 512;       // partition workgroup
 constexpr int kPIPT = 4;        // tuples per thread per tile
 constexpr int kPTile = kPNT * kPIPT;
 constexpr uint32_t kChunk = 16384;  // tuples per partitioning workgroup (one histogram)
-constexpr int kMaxPassBits = 9;     // buckets per pass <= kPNT
+constexpr int kMaxPassBits = 10;    // at most 1024 buckets per pass
+constexpr int kMaxB = 1 << kMaxPassBits;
+constexpr int kBPT = kMaxB / kPNT;  // buckets owned by each thread in the tile scan
 
 constexpr int kJNT = 512;       // join workgroup
 constexpr int kJIPT = 4;
@@ -92,6 +94,27 @@ __global__ void __launch_bounds__(kPNT)
 }
 
 template <typename K, typename P, bool kRows>
+__device__ __forceinline__ void load_part_tile(K (&key)[kPIPT], P (&pay)[kPIPT], uint32_t (&row)[kPIPT],
+                                               const K *__restrict__ keys, const P *__restrict__ pays,
+                                               const uint32_t *__restrict__ rows, uint32_t t0,
+                                               uint32_t hi) {
+#pragma unroll
+  for (int k = 0; k < kPIPT; ++k) {
+    const uint32_t i = t0 + k * kPNT + threadIdx.x;
+    if (i < hi) {
+      key[k] = keys[i];
+      pay[k] = pays[i];
+      row[k] = kRows ? rows[i] : i;
+    }
+  }
+}
+
+// Scatter one chunk into its partitions. Per tile of kPTile tuples: rank each
+// tuple within its bucket (LDS atomics), scan the tile histogram, sort the tile
+// by bucket in LDS, then write each bucket's run to its output position, so
+// consecutive threads store consecutive addresses. The next tile's loads are
+// issued before the current tile's LDS phases.
+template <typename K, typename P, bool kRows>
 __global__ void __launch_bounds__(kPNT)
     k_part_scatter(const K *__restrict__ keys, const P *__restrict__ pays,
                    const uint32_t *__restrict__ rows, const uint32_t *__restrict__ seg_off,
@@ -102,7 +125,7 @@ __global__ void __launch_bounds__(kPNT)
   __shared__ P lp[kPTile];
   __shared__ uint32_t lr[kPTile];
   __shared__ uint16_t lb[kPTile];
-  __shared__ uint32_t hist[1 << kMaxPassBits], loff[1 << kMaxPassBits], gcur[1 << kMaxPassBits];
+  __shared__ uint32_t hist[kMaxB], gcur[kMaxB], gdst[kMaxB], loff[kMaxB];
   __shared__ uint32_t scan_tmp[kPNT / 64 + 1];
   const uint32_t c = blockIdx.x;
   if (c >= cpre[nseg]) return;
@@ -115,29 +138,45 @@ __global__ void __launch_bounds__(kPNT)
     hist[b] = 0;
     gcur[b] = C[uint64_t(cpre[s]) * B + uint64_t(b) * nch + lc];
   }
+  K key[kPIPT], nkey[kPIPT];
+  P pay[kPIPT], npay[kPIPT];
+  uint32_t row[kPIPT], nrow[kPIPT];
+  load_part_tile<K, P, kRows>(key, pay, row, keys, pays, rows, lo, hi);
   __syncthreads();
   for (uint32_t t0 = lo; t0 < hi; t0 += kPTile) {
     const uint32_t t1 = min(hi, t0 + kPTile);
-    K key[kPIPT];
-    P pay[kPIPT];
-    uint32_t row[kPIPT], bk[kPIPT], rk[kPIPT];
+    uint32_t bk[kPIPT], rk[kPIPT];
 #pragma unroll
     for (int k = 0; k < kPIPT; ++k) {
       const uint32_t i = t0 + k * kPNT + threadIdx.x;
       if (i < t1) {
-        key[k] = keys[i];
-        pay[k] = pays[i];
-        row[k] = kRows ? rows[i] : i;
         bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
         rk[k] = atomicAdd(&hist[bk[k]], 1u);
       }
     }
+    if (t0 + kPTile < hi) load_part_tile<K, P, kRows>(nkey, npay, nrow, keys, pays, rows, t0 + kPTile, hi);
     __syncthreads();
-    // exclusive scan of the tile histogram (B <= kPNT: one bucket per thread)
+    // scan of the tile histogram; each thread owns kBPT consecutive buckets
+    uint32_t v[kBPT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kBPT; ++j) {
+      const uint32_t b = threadIdx.x * kBPT + j;
+      v[j] = b < B ? hist[b] : 0u;
+      sum += v[j];
+    }
     uint32_t total;
-    const uint32_t h = threadIdx.x < B ? hist[threadIdx.x] : 0u;
-    const uint32_t ex = block_exclusive_scan<kPNT>(h, scan_tmp, &total);
-    if (threadIdx.x < B) loff[threadIdx.x] = ex;
+    uint32_t ex = block_exclusive_scan<kPNT>(sum, scan_tmp, &total);
+#pragma unroll
+    for (int j = 0; j < kBPT; ++j) {
+      const uint32_t b = threadIdx.x * kBPT + j;
+      if (b < B) {
+        loff[b] = ex;
+        gdst[b] = gcur[b] - ex;  // output position of tile slot e of bucket b: gdst[b] + e
+        gcur[b] += v[j];
+        hist[b] = 0;
+        ex += v[j];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kPIPT; ++k) {
@@ -153,18 +192,181 @@ __global__ void __launch_bounds__(kPNT)
     __syncthreads();
     const uint32_t n = t1 - t0;
     for (uint32_t e = threadIdx.x; e < n; e += kPNT) {
-      const uint32_t b = lb[e];
-      const uint32_t dst = gcur[b] + (e - loff[b]);
+      const uint32_t dst = gdst[lb[e]] + e;
       okeys[dst] = lk[e];
       opays[dst] = lp[e];
       orows[dst] = lr[e];
     }
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      key[k] = nkey[k];
+      pay[k] = npay[k];
+      row[k] = nrow[k];
+    }
+    // The next tile's first LDS writes are its hist atomics (hist was cleared
+    // above); gdst/loff/lk are rewritten only after the next barrier.
+  }
+}
+
+// Write-combining scatter for up to MAXB buckets. Same tile sort as
+// k_part_scatter, but a bucket's tuples are written only in whole groups of
+// kWcGroup tuples that end on a kWcGroup-aligned output index (a 128-byte
+// line of the 8-byte arrays); the remainder waits in a per-bucket LDS buffer
+// for the next tile. Only the first and last line of a chunk's run in a
+// bucket can be partial, so memory sees whole-line writes (HBM3E has no write
+// mask, and partial lines cost a read-modify-write).
+constexpr int kWcGroup = 16;
+
+template <typename K, typename P, bool kRows, int MAXB>
+__global__ void __launch_bounds__(kPNT)
+    k_part_scatter_wc(const K *__restrict__ keys, const P *__restrict__ pays,
+                      const uint32_t *__restrict__ rows, const uint32_t *__restrict__ seg_off,
+                      const uint32_t *__restrict__ cpre, uint32_t nseg, int shift, int bits,
+                      const uint32_t *__restrict__ C, K *__restrict__ okeys, P *__restrict__ opays,
+                      uint32_t *__restrict__ orows) {
+  constexpr int G = kWcGroup;
+  __shared__ K lk[kPTile];
+  __shared__ P lp[kPTile];
+  __shared__ uint32_t lr[kPTile];
+  __shared__ K qk[MAXB * G];
+  __shared__ P qp[MAXB * G];
+  __shared__ uint32_t qr[MAXB * G];
+  __shared__ uint32_t hist[MAXB], loff[MAXB], gcur[MAXB], pend[MAXB], emit[MAXB], eoff[MAXB + 1];
+  const uint32_t c = blockIdx.x;
+  if (c >= cpre[nseg]) return;
+  const uint32_t B = 1u << bits;
+  const uint32_t s = find_segment(cpre, nseg, c);
+  const uint32_t lc = c - cpre[s], nch = cpre[s + 1] - cpre[s];
+  const uint32_t lo = seg_off[s] + lc * kChunk;
+  const uint32_t hi = min(seg_off[s + 1], lo + kChunk);
+  for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
+    hist[b] = 0;
+    pend[b] = 0;
+    gcur[b] = C[uint64_t(cpre[s]) * B + uint64_t(b) * nch + lc];
+  }
+  K key[kPIPT], nkey[kPIPT];
+  P pay[kPIPT], npay[kPIPT];
+  uint32_t row[kPIPT], nrow[kPIPT];
+  load_part_tile<K, P, kRows>(key, pay, row, keys, pays, rows, lo, hi);
+  __syncthreads();
+  for (uint32_t t0 = lo; t0 < hi; t0 += kPTile) {
+    const uint32_t t1 = min(hi, t0 + kPTile);
+    uint32_t bk[kPIPT], rk[kPIPT];
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      const uint32_t i = t0 + k * kPNT + threadIdx.x;
+      if (i < t1) {
+        bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
+        rk[k] = atomicAdd(&hist[bk[k]], 1u);
+      }
+    }
+    if (t0 + kPTile < hi) load_part_tile<K, P, kRows>(nkey, npay, nrow, keys, pays, rows, t0 + kPTile, hi);
     __syncthreads();
-    for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
-      gcur[b] += hist[b];
-      hist[b] = 0;
+    // wave 0: exclusive scans of the tile histogram (-> loff) and of the
+    // tuples each bucket emits this tile (-> eoff); lane l owns MAXB/64 buckets
+    if (threadIdx.x < 64) {
+      constexpr int PER = MAXB / 64;
+      uint32_t h[PER], e[PER], hs = 0, es = 0;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t b = threadIdx.x * PER + j;
+        h[j] = b < B ? hist[b] : 0u;
+        e[j] = 0;
+        if (b < B) {
+          const uint32_t end = (gcur[b] + pend[b] + h[j]) & ~uint32_t(G - 1);
+          e[j] = end > gcur[b] ? end - gcur[b] : 0u;
+        }
+        hs += h[j];
+        es += e[j];
+      }
+      const uint32_t hx = wave_inclusive_scan(hs) - hs;
+      const uint32_t ex = wave_inclusive_scan(es) - es;
+      uint32_t hr = hx, er = ex;
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const uint32_t b = threadIdx.x * PER + j;
+        if (b < B) {
+          loff[b] = hr;
+          eoff[b] = er;
+          emit[b] = e[j];
+        }
+        hr += h[j];
+        er += e[j];
+      }
+      if (threadIdx.x == 63) eoff[B] = er;
     }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      const uint32_t i = t0 + k * kPNT + threadIdx.x;
+      if (i < t1) {
+        const uint32_t pos = loff[bk[k]] + rk[k];
+        lk[pos] = key[k];
+        lp[pos] = pay[k];
+        lr[pos] = row[k];
+      }
+    }
+    __syncthreads();
+    // emit whole groups: pending tuples first, then the head of the tile run
+    const uint32_t etot = eoff[B];
+    for (uint32_t e = threadIdx.x; e < etot; e += kPNT) {
+      uint32_t l = 0, r = B;  // eoff[l] <= e < eoff[r]
+      while (r - l > 1) {
+        const uint32_t m = (l + r) / 2;
+        if (eoff[m] <= e) l = m; else r = m;
+      }
+      const uint32_t b = l, k = e - eoff[b], pb = pend[b];
+      const uint32_t dst = gcur[b] + k;
+      if (k < pb) {
+        okeys[dst] = qk[b * G + k];
+        opays[dst] = qp[b * G + k];
+        orows[dst] = qr[b * G + k];
+      } else {
+        const uint32_t src = loff[b] + (k - pb);
+        okeys[dst] = lk[src];
+        opays[dst] = lp[src];
+        orows[dst] = lr[src];
+      }
+    }
+    __syncthreads();
+    // keep the remainder (fewer than G tuples) for the next tile
+    for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
+      const uint32_t pb = pend[b], h = hist[b], e = emit[b];
+      if (e == 0) {
+        for (uint32_t i = 0; i < h; ++i) {
+          qk[b * G + pb + i] = lk[loff[b] + i];
+          qp[b * G + pb + i] = lp[loff[b] + i];
+          qr[b * G + pb + i] = lr[loff[b] + i];
+        }
+        pend[b] = pb + h;
+      } else {
+        const uint32_t keep = pb + h - e;  // < G; all pending tuples were emitted
+        for (uint32_t i = 0; i < keep; ++i) {
+          qk[b * G + i] = lk[loff[b] + h - keep + i];
+          qp[b * G + i] = lp[loff[b] + h - keep + i];
+          qr[b * G + i] = lr[loff[b] + h - keep + i];
+        }
+        pend[b] = keep;
+        gcur[b] += e;
+      }
+      hist[b] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      key[k] = nkey[k];
+      pay[k] = npay[k];
+      row[k] = nrow[k];
+    }
+    __syncthreads();
+  }
+  // chunk end: the remaining tuples of every bucket
+  for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
+    for (uint32_t i = 0; i < pend[b]; ++i) {
+      const uint32_t dst = gcur[b] + i;
+      okeys[dst] = qk[b * G + i];
+      opays[dst] = qp[b * G + i];
+      orows[dst] = qr[b * G + i];
+    }
   }
 }
 
@@ -195,16 +397,30 @@ __global__ void k_items(const uint32_t *__restrict__ offR, const uint32_t *__res
 }
 
 template <typename K, typename PB>
+struct LdsSlot {
+  K key;
+  uint32_t rowid;
+  PB pay;
+};
+
+// LDS latency is short, so LDS tables walk one row at a time (kHashed = false)
+// and keep registers for occupancy.
+template <typename K, typename PB>
 struct LdsTab {
+  static constexpr bool kHashed = false;
+  using SlotT = LdsSlot<K, PB>;
   K *tk;
   uint32_t *tr;
   PB *tp;
   uint32_t nslots;
+  bool unique;
 
   __device__ __forceinline__ uint32_t home(K key) const {
     const uint32_t h = static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))));
     return static_cast<uint32_t>((uint64_t(h) * nslots) >> 32);
   }
+  __device__ __forceinline__ uint32_t next(uint32_t i) const { return (i + 1 == nslots) ? 0 : i + 1; }
+  __device__ __forceinline__ SlotT load(uint32_t i) const { return SlotT{tk[i], tr[i], tp[i]}; }
   __device__ __forceinline__ uint32_t lookup(K key, uint32_t &first, uint64_t &psum) const {
     uint32_t i = home(key), c = 0;
     for (;;) {
@@ -214,8 +430,9 @@ struct LdsTab {
         first = r;
         psum += static_cast<uint64_t>(sext(tp[i]));
         ++c;
+        if (unique) break;
       }
-      i = (i + 1 == nslots) ? 0 : i + 1;
+      i = next(i);
     }
     return c;
   }
@@ -226,7 +443,7 @@ struct LdsTab {
       const uint32_t r = tr[i];
       if (r == kEmpty) break;
       if (tk[i] == key) f(r);
-      i = (i + 1 == nslots) ? 0 : i + 1;
+      i = next(i);
     }
   }
 };
@@ -248,7 +465,7 @@ __global__ void __launch_bounds__(kJNT)
   __shared__ uint32_t tr[MAXS];
   __shared__ PB tp[MAXS];
   __shared__ EmitLds<kJNT, kJSCAP> L;
-  uint32_t fill = 0;
+  uint64_t fill = 0;
   uint64_t cs = 0;
   const uint32_t nitems = item_off[F];
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -270,7 +487,9 @@ __global__ void __launch_bounds__(kJNT)
       ns = ns < 64 ? 64 : (ns > MAXS ? MAXS : ns);
       for (uint32_t i = threadIdx.x; i < ns; i += kJNT) tr[i] = kEmpty;
       __syncthreads();
-      LdsTab<K, PB> tab{tk, tr, tp, ns};
+      __shared__ uint32_t dup;
+      if (threadIdx.x == 0) dup = 0;
+      LdsTab<K, PB> tab{tk, tr, tp, ns, false};
       for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
         const K key = rk[j];
         uint32_t i = tab.home(key);
@@ -284,8 +503,15 @@ __global__ void __launch_bounds__(kJNT)
         }
       }
       __syncthreads();
-      for (uint32_t t = s0; t < s1; t += kJNT * kJIPT)
-        probe_tile<kJNT, kJIPT, kJSCAP>(tab, sk, sp, sr, t, min(s1, t + kJNT * kJIPT), L, fill, o, cs);
+      // distinct build keys in this table let probes stop at their first match
+      for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
+        uint32_t cnt = 0;
+        tab.for_each(rk[j], [&](uint32_t) { ++cnt; });
+        if (cnt > 1) dup = 1;
+      }
+      __syncthreads();
+      tab.unique = dup == 0;
+      probe_range<kJNT, kJIPT, kJSCAP>(tab, sk, sp, sr, s0, s1, L, fill, o, cs);
       __syncthreads();
     }
   }
@@ -324,6 +550,13 @@ PassPlan split_bits(int bits, int passes) {
 
 uint64_t ub_chunks(uint64_t n, uint32_t nseg) { return (n + kChunk - 1) / kChunk + nseg; }
 
+unsigned grid_for_rows(uint64_t n) {
+  uint64_t g = (n + 511) / 512;
+  const uint64_t cap = uint64_t(device_cu_count()) * 8;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g ? g : 1);
+}
+
 // One partitioning pass of n tuples from `in` into `out`. Segments are given by
 // seg_off/cpre (device, nseg + 1 entries each); on return part_off (device,
 // nseg * 2^bits + 1 entries) holds the partition boundaries.
@@ -338,8 +571,16 @@ int part_pass(const K *ik, const P *ip, const uint32_t *ir, Side<K, P> out, uint
   EIGER_LAUNCH("radix_hist", k_part_hist<K>, dim3(unsigned(ub)), dim3(kPNT), 0, s, ik, seg_off, cpre,
                nseg, shift, bits, C);
   if ((rc = exclusive_scan_u32(C, C, nC, tmp, total, s))) return rc;
-  EIGER_LAUNCH("radix_scatter", (k_part_scatter<K, P, kRows>), dim3(unsigned(ub)), dim3(kPNT), 0, s,
-               ik, ip, ir, seg_off, cpre, nseg, shift, bits, C, out.k, out.p, out.r);
+  if (bits <= 7) {
+    EIGER_LAUNCH("radix_scatter", (k_part_scatter_wc<K, P, kRows, 128>), dim3(unsigned(ub)), dim3(kPNT), 0,
+                 s, ik, ip, ir, seg_off, cpre, nseg, shift, bits, C, out.k, out.p, out.r);
+  } else if (bits <= 8) {
+    EIGER_LAUNCH("radix_scatter", (k_part_scatter_wc<K, P, kRows, 256>), dim3(unsigned(ub)), dim3(kPNT), 0,
+                 s, ik, ip, ir, seg_off, cpre, nseg, shift, bits, C, out.k, out.p, out.r);
+  } else {
+    EIGER_LAUNCH("radix_scatter", (k_part_scatter<K, P, kRows>), dim3(unsigned(ub)), dim3(kPNT), 0, s,
+                 ik, ip, ir, seg_off, cpre, nseg, shift, bits, C, out.k, out.p, out.r);
+  }
   const uint64_t nq = (uint64_t(nseg) << bits) + 1;
   EIGER_LAUNCH("radix_offsets", k_part_offsets, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s,
                seg_off, cpre, nseg, bits, C, part_off, static_cast<uint32_t>(n));
@@ -462,6 +703,242 @@ RadixLimits radix_limits(int32_t kdt, int32_t bpdt, float lf) {
 int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   const bool k64 = a.kdt == EIGER_INT64, b64 = a.bpdt == EIGER_INT64, p64 = a.ppdt == EIGER_INT64;
 #define EIGER_DISPATCH(KT, BT, PT) return radix_impl<KT, BT, PT>(a, ws, ctr)
+  if (!k64 && !b64 && !p64) EIGER_DISPATCH(int32_t, int32_t, int32_t);
+  if (!k64 && !b64 && p64) EIGER_DISPATCH(int32_t, int32_t, int64_t);
+  if (!k64 && b64 && !p64) EIGER_DISPATCH(int32_t, int64_t, int32_t);
+  if (!k64 && b64 && p64) EIGER_DISPATCH(int32_t, int64_t, int64_t);
+  if (k64 && !b64 && !p64) EIGER_DISPATCH(int64_t, int32_t, int32_t);
+  if (k64 && !b64 && p64) EIGER_DISPATCH(int64_t, int32_t, int64_t);
+  if (k64 && b64 && !p64) EIGER_DISPATCH(int64_t, int64_t, int32_t);
+  EIGER_DISPATCH(int64_t, int64_t, int64_t);
+#undef EIGER_DISPATCH
+}
+
+}  // namespace eiger
+
+// ============================================================================
+// RADIX_CACHE: one partitioning pass over the probe side; the build side goes
+// into ONE table laid out partition-major (partition p owns slots
+// [table_off[p], table_off[p+1])), each region sized to stay in an XCD's L2.
+// Probe tiles are taken in partition order and split into eight contiguous
+// ranges, one per XCD (workgroup w runs on XCD w % 8 under round-robin
+// dispatch), so the workgroups of an XCD work on one partition at a time and
+// its table region is read from that XCD's L2.
+// ============================================================================
+namespace eiger {
+namespace {
+
+constexpr int kCNT = 256;
+constexpr int kCIPT = 8;
+constexpr int kCSCAP = 4096;
+constexpr uint32_t kCTileMax = 16384;  // probe rows per work item (upper bound)
+constexpr int kXcds = 8;
+constexpr double kL2RegionMax = 3.0 * 1024 * 1024;  // larger regions use the shared schedule
+
+__device__ __forceinline__ uint32_t fastrange32(uint64_t h, uint32_t n) {
+  return static_cast<uint32_t>((uint64_t(static_cast<uint32_t>(h)) * n) >> 32);
+}
+
+template <typename K, typename PB>
+struct CacheTab {
+  static constexpr bool kHashed = true;
+  using SlotT = Slot<K, PB>;
+  const Slot<K, PB> *__restrict__ slots;
+  uint32_t n;
+  bool unique;
+
+  __device__ __forceinline__ uint32_t home(K key) const {
+    return fastrange32(fmix64(static_cast<uint64_t>(sext(key))), n);
+  }
+  __device__ __forceinline__ uint32_t next(uint32_t i) const { return (i + 1 == n) ? 0 : i + 1; }
+  __device__ __forceinline__ SlotT load(uint32_t i) const { return slots[i]; }
+  template <class F>
+  __device__ __forceinline__ void for_each(K key, F f) const {
+    uint32_t i = home(key);
+    for (;;) {
+      const Slot<K, PB> s = slots[i];
+      if (s.rowid == kEmpty) break;
+      if (s.key == key) f(s.rowid);
+      i = next(i);
+    }
+  }
+};
+
+// Sets *dup when some build key occurs twice (each build row counts its key in
+// its partition's region).
+template <typename K, typename PB>
+__global__ void k_cache_unique(const K *__restrict__ keys, uint64_t n, int bits,
+                               const uint32_t *__restrict__ table_off,
+                               const Slot<K, PB> *__restrict__ table, uint32_t *dup) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+    if (*static_cast<volatile uint32_t *>(dup)) return;
+    const K key = keys[r];
+    const uint32_t p = static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) >> (64 - bits));
+    CacheTab<K, PB> tab{table + table_off[p], table_off[p + 1] - table_off[p], false};
+    uint32_t c = 0;
+    tab.for_each(key, [&](uint32_t) { ++c; });
+    if (c > 1) atomicOr(dup, 1u);
+  }
+}
+
+// Slots of each partition's region (at least one more than its rows, so every
+// probe walk ends at an empty slot) and probe tiles per partition.
+__global__ void k_cache_sizes(const uint32_t *__restrict__ offR, const uint32_t *__restrict__ offS,
+                              uint32_t F, float lf, uint32_t ctile, uint32_t *__restrict__ tsz,
+                              uint32_t *__restrict__ tiles) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < F) {
+    const uint32_t nr = offR[p + 1] - offR[p], ns = offS[p + 1] - offS[p];
+    tsz[p] = nr ? static_cast<uint32_t>(ceil(static_cast<double>(nr) / static_cast<double>(lf))) + 1u : 0u;
+    if (nr && tsz[p] <= nr) tsz[p] = nr + 1;
+    tiles[p] = (nr && ns) ? (ns + ctile - 1) / ctile : 0u;
+  }
+  if (p == F) {
+    tsz[p] = 0;
+    tiles[p] = 0;
+  }
+}
+
+template <typename K, typename PB>
+__global__ void k_cache_build(const K *__restrict__ keys, const PB *__restrict__ pay, uint64_t n,
+                              int bits, const uint32_t *__restrict__ table_off,
+                              Slot<K, PB> *__restrict__ table) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const K key = keys[r];
+    const uint64_t h = fmix64(static_cast<uint64_t>(sext(key)));
+    const uint32_t p = static_cast<uint32_t>(h >> (64 - bits));
+    const uint32_t base = table_off[p], ns = table_off[p + 1] - base;
+    uint32_t i = fastrange32(h, ns);
+    for (;;) {
+      if (atomicCAS(&table[base + i].rowid, kEmpty, static_cast<uint32_t>(r)) == kEmpty) {
+        table[base + i].key = key;
+        table[base + i].pay = pay[r];
+        break;
+      }
+      i = (i + 1 == ns) ? 0 : i + 1;
+    }
+  }
+}
+
+template <typename K, typename PB, typename PS>
+__global__ void __launch_bounds__(kCNT)
+    k_cache_probe(const Slot<K, PB> *__restrict__ table, const uint32_t *__restrict__ table_off,
+                  const K *__restrict__ sk, const PS *__restrict__ sp, const uint32_t *__restrict__ sr,
+                  const uint32_t *__restrict__ offS, const uint32_t *__restrict__ tile_off, uint32_t F,
+                  uint32_t per_xcd, uint32_t ctile, int shared_mall, const uint32_t *dup, EmitOut o) {
+  __shared__ EmitLds<kCNT, kCSCAP> L;
+  uint64_t fill = 0;
+  uint64_t cs = 0;
+  const bool unique = *dup == 0;
+  const uint64_t T = tile_off[F];
+  // L2 schedule: XCD x takes the x-th eighth of the tiles (its own partitions).
+  // Shared schedule (regions too big for an L2): consecutive tiles go to
+  // consecutive workgroups, so every XCD works on the same partition and its
+  // region stays in the memory-side cache.
+  const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+  const uint64_t xlo = shared_mall ? blockIdx.x : T * x / kXcds + j;
+  const uint64_t xhi = shared_mall ? T : T * (x + 1) / kXcds;
+  const uint64_t step = shared_mall ? gridDim.x : per_xcd;
+  for (uint64_t t = xlo; t < xhi; t += step) {
+    uint32_t lo = 0, hi = F;  // tile_off[lo] <= t < tile_off[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (tile_off[mid] <= t) lo = mid; else hi = mid;
+    }
+    const uint32_t p = lo;
+    const uint32_t s0 = offS[p] + static_cast<uint32_t>(t - tile_off[p]) * ctile;
+    const uint32_t s1 = min(offS[p + 1], s0 + ctile);
+    CacheTab<K, PB> tab{table + table_off[p], table_off[p + 1] - table_off[p], unique};
+    probe_range<kCNT, kCIPT, kCSCAP>(tab, sk, sp, sr, s0, s1, L, fill, o, cs);
+  }
+  finish(L, o, fill, cs);
+}
+
+uint64_t cache_table_bound(uint64_t nR, float lf, uint32_t F) {
+  return static_cast<uint64_t>(static_cast<double>(nR) / static_cast<double>(lf)) + 2ull * F + 64;
+}
+
+template <typename K, typename PB, typename PS>
+int radix_cache_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
+  int bits = a.plan.radix_bits;
+  if (bits < 1) bits = 1;
+  if (bits > kCacheMaxBits) bits = kCacheMaxBits;
+  const uint32_t F = 1u << bits;
+  float lf = a.plan.load_factor;
+  if (!(lf > 0.f) || lf > 0.9f) lf = 0.5f;
+  const PassPlan pp{{bits, 0}, 1};
+  const uint64_t tbound = cache_table_bound(a.nR, lf, F);
+  if (tbound >= (uint64_t(1) << 32))
+    return fail(EIGER_ERR_TOO_LARGE, "RADIX_CACHE: table above 2^32 slots; raise the load factor");
+
+  JoinCounters *c = ws.take<JoinCounters>(1);
+  SideBufs<K, PS> S = side_layout<K, PS>(ws, a.nS, pp);
+  uint32_t *seg1 = ws.take<uint32_t>(2), *cpre1 = ws.take<uint32_t>(2);
+  uint32_t *offR = ws.take<uint32_t>(F + 1);
+  const uint64_t nC = std::max(ub_chunks(a.nR, 1), ub_chunks(a.nS, 1)) << bits;
+  uint32_t *C = ws.take<uint32_t>(nC);
+  uint64_t *tmp = ws.take<uint64_t>(scan_tmp_elems(std::max<uint64_t>(nC, F + 1)));
+  uint64_t *total = ws.take<uint64_t>(1);
+  uint32_t *table_off = ws.take<uint32_t>(F + 1);
+  uint32_t *tile_off = ws.take<uint32_t>(F + 1);
+  uint32_t *dup = ws.take<uint32_t>(1);
+  Slot<K, PB> *table = ws.take<Slot<K, PB>>(tbound);
+  *ctr = c;
+  if (!ws.base) return EIGER_OK;
+  hipStream_t s = a.s;
+  int rc;
+  if ((rc = fill_u64(reinterpret_cast<uint64_t *>(c), 4, 0, s))) return rc;
+  if (a.nR == 0 || a.nS == 0) return EIGER_OK;
+  const K *bk = static_cast<const K *>(a.bk);
+  // build side: partition sizes only (histogram + scan), no scatter
+  EIGER_LAUNCH("radix_seg", k_single_segment, dim3(1), dim3(64), 0, s, seg1, cpre1,
+               static_cast<uint32_t>(a.nR));
+  {
+    const uint64_t ub = ub_chunks(a.nR, 1), nCR = ub << bits;
+    if ((rc = fill_u32(C, nCR, 0, s))) return rc;
+    EIGER_LAUNCH("radix_hist", k_part_hist<K>, dim3(unsigned(ub)), dim3(kPNT), 0, s, bk, seg1, cpre1, 1u,
+                 64 - bits, bits, C);
+    if ((rc = exclusive_scan_u32(C, C, nCR, tmp, total, s))) return rc;
+    EIGER_LAUNCH("radix_offsets", k_part_offsets, dim3(unsigned((F + 1 + 255) / 256)), dim3(256), 0, s,
+                 seg1, cpre1, 1u, bits, C, offR, static_cast<uint32_t>(a.nR));
+  }
+  // probe side: one partitioning pass
+  Side<K, PS> fs;
+  if ((rc = partition_side<K, PS>(static_cast<const K *>(a.pk), static_cast<const PS *>(a.pp), a.nS, S,
+                                  pp, C, tmp, total, s, &fs)))
+    return rc;
+  // The workgroups of one XCD should cover about one partition at a time, so
+  // that a single table region is live in that XCD's L2.
+  const uint32_t per_xcd = static_cast<uint32_t>(std::max(1, device_cu_count() / kXcds)) * 4;
+  const double region = static_cast<double>(a.nR) / F / lf * sizeof(Slot<K, PB>);
+  const int shared_mall = region > kL2RegionMax ? 1 : 0;
+  uint64_t ct = shared_mall ? kCTileMax : a.nS / F / per_xcd;
+  ct = std::max<uint64_t>(2048, std::min<uint64_t>(kCTileMax, ct));
+  const uint32_t ctile = static_cast<uint32_t>((ct + 2047) / 2048 * 2048);
+  EIGER_LAUNCH("cache_sizes", k_cache_sizes, dim3((F + 1 + 255) / 256), dim3(256), 0, s, offR, S.off, F,
+               lf, ctile, table_off, tile_off);
+  if ((rc = exclusive_scan_u32(table_off, table_off, F + 1, tmp, total, s))) return rc;
+  if ((rc = exclusive_scan_u32(tile_off, tile_off, F + 1, tmp, total, s))) return rc;
+  if ((rc = fill_u32(reinterpret_cast<uint32_t *>(table), tbound * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
+    return rc;
+  EIGER_LAUNCH("cache_build", (k_cache_build<K, PB>), dim3(grid_for_rows(a.nR)), dim3(256), 0, s, bk,
+               static_cast<const PB *>(a.bp), a.nR, bits, table_off, table);
+  if ((rc = fill_u32(dup, 1, 0, s))) return rc;
+  EIGER_LAUNCH("cache_unique", (k_cache_unique<K, PB>), dim3(grid_for_rows(a.nR)), dim3(256), 0, s, bk, a.nR,
+               bits, table_off, table, dup);
+  EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
+  EIGER_LAUNCH("cache_probe", (k_cache_probe<K, PB, PS>), dim3(per_xcd * kXcds), dim3(kCNT), 0, s, table,
+               table_off, fs.k, fs.p, fs.r, S.off, tile_off, F, per_xcd, ctile, shared_mall, dup, o);
+  return EIGER_OK;
+}
+
+}  // namespace
+
+int run_radix_cache(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
+  const bool k64 = a.kdt == EIGER_INT64, b64 = a.bpdt == EIGER_INT64, p64 = a.ppdt == EIGER_INT64;
+#define EIGER_DISPATCH(KT, BT, PT) return radix_cache_impl<KT, BT, PT>(a, ws, ctr)
   if (!k64 && !b64 && !p64) EIGER_DISPATCH(int32_t, int32_t, int32_t);
   if (!k64 && !b64 && p64) EIGER_DISPATCH(int32_t, int32_t, int64_t);
   if (!k64 && b64 && !p64) EIGER_DISPATCH(int32_t, int64_t, int32_t);

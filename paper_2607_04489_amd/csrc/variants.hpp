@@ -31,6 +31,7 @@ constexpr uint64_t kFlagBuildOutOfRange = 1;  // DIRECT: a build key outside [bu
 int run_direct(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_global_hash(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+int run_radix_cache(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 
 // Largest key range the DIRECT variant accepts (its offset table is 4 B per key value).
 constexpr uint64_t kDirectMaxRange = uint64_t(1) << 30;
@@ -44,5 +45,12 @@ struct RadixLimits {
   uint32_t max_build;   // build rows one LDS table holds at load factor lf
 };
 RadixLimits radix_limits(int32_t kdt, int32_t bpdt, float lf);
+
+// RADIX_CACHE: largest partition-bit count of its single partitioning pass.
+constexpr int kCacheMaxBits = 10;
+// Bytes of one slot of the device-memory hash tables (GLOBAL_HASH, RADIX_CACHE).
+inline size_t slot_bytes(int32_t kdt, int32_t bpdt) {
+  return (dtype_size(kdt) + dtype_size(bpdt) + 4 <= 16) ? 16 : 32;
+}
 
 }  // namespace eiger

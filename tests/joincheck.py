@@ -16,6 +16,9 @@ SPECS = [
     ("radix_b9", eg.RADIX, 9, 1, 0.75),
     ("radix_b10p2", eg.RADIX, 10, 2, 0.5),
     ("radix_b15p2", eg.RADIX, 15, 2, 0.6),
+    ("cache_b1", eg.RADIX_CACHE, 1, 1, 0.5),
+    ("cache_b6", eg.RADIX_CACHE, 6, 1, 0.75),
+    ("cache_b10", eg.RADIX_CACHE, 10, 1, 0.5),
 ]
 SPEC_IDS = [s[0] for s in SPECS]
 

@@ -59,12 +59,16 @@ def test_rule_plan_sparse_small_is_global_hash(lib):
     assert p.variant == eg.GLOBAL_HASH and 0 < p.load_factor <= 0.9
 
 
-def test_rule_plan_sparse_large_is_radix(lib):
+def test_rule_plan_sparse_large(lib):
+    # a 1 GiB table is still probed faster in place than partitioned
     p = plan(stats(1 << 24, -(1 << 63), (1 << 63) - 1, 1.6e7, eg.INT64),
              stats(1 << 29, -(1 << 63), (1 << 63) - 1, 1.6e7, eg.INT64))
-    assert p.variant == eg.RADIX
+    assert p.variant == eg.GLOBAL_HASH
+    # beyond the table budget the join partitions
+    p = plan(stats(1 << 28, -(1 << 63), (1 << 63) - 1, 2.6e8, eg.INT64),
+             stats(1 << 29, -(1 << 63), (1 << 63) - 1, 2.6e8, eg.INT64))
+    assert p.variant in (eg.RADIX, eg.RADIX_CACHE)
     assert 1 <= p.radix_bits <= 18 and p.radix_passes in (1, 2)
-    assert p.radix_passes == 2 or p.radix_bits <= 9
 
 
 def test_fixed_hash_and_forced(lib):
@@ -131,7 +135,7 @@ def test_workspace_sizes_grow_with_inputs(lib):
     b = stats(1 << 20, -(1 << 40), 1 << 40, 1e6, eg.INT64)
     s = stats(1 << 24, -(1 << 40), 1 << 40, 1e6, eg.INT64)
     sizes = []
-    for v, bits, passes in [(eg.GLOBAL_HASH, 0, 0), (eg.RADIX, 8, 1), (eg.RADIX, 12, 2)]:
+    for v, bits, passes in [(eg.GLOBAL_HASH, 0, 0), (eg.RADIX, 8, 1), (eg.RADIX, 12, 2), (eg.RADIX_CACHE, 8, 1)]:
         p = plan(b, s, eg.SEL_FORCED, eg.make_plan(v, bits, passes, 0.5))
         small = ctypes.c_size_t()
         big = ctypes.c_size_t()
@@ -143,6 +147,7 @@ def test_workspace_sizes_grow_with_inputs(lib):
         sizes.append(big.value)
     # a two-pass radix join keeps two partitioned copies of each side
     assert sizes[2] > sizes[1] > sizes[0]
+    assert sizes[3] > sizes[0]
 
 
 def test_stats_empty_column_needs_no_gpu(lib):
