@@ -23,6 +23,92 @@ sys.path.insert(0, ROOT)
 
 METRIC = "probe tuples/s + HBM GB/s % peak; learned/batched vs fixed hash join"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_2607_04489_amd", "csrc")
+# Sources that define each timed kernel: a traffic record is valid only while they are unchanged.
+KERNEL_SOURCES = {
+    "hash_probe": ["join_hash.hip", "join_common.hpp", "common.hpp"],
+    "hash_build": ["join_hash.hip", "join_common.hpp", "common.hpp"],
+    "direct_probe": ["join_direct.hip", "join_common.hpp", "common.hpp"],
+    "radix_scatter": ["join_radix.hip", "join_common.hpp", "common.hpp"],
+    "radix_join": ["join_radix.hip", "join_common.hpp", "common.hpp"],
+    "radix_hist": ["join_radix.hip", "common.hpp"],
+    "cache_probe": ["join_radix.hip", "join_common.hpp", "common.hpp"],
+    "stats_partial": ["stats.hip", "common.hpp"],
+}
+# Kernel symbol fragments of each timed name (to find them in rocprofv3 output).
+KERNEL_SYMBOLS = {
+    "hash_probe": "k_probe<eiger::(anonymous namespace)::HashTab", "hash_build": "k_hash_build",
+    "direct_probe": "k_probe<eiger::(anonymous namespace)::DirectTab", "radix_scatter": "k_part_scatter",
+    "radix_join": "k_radix_join", "radix_hist": "k_part_hist", "cache_probe": "k_cache_probe",
+    "stats_partial": "k_stats_partial",
+}
+
+
+def sources_digest(name):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(name, []):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(name, workload):
+    """HBM bytes per launch of `name` from the committed rocprofv3 counter
+    record, or None when there is none or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(name)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("workload") != workload or rec.get("sources_sha") != sources_digest(name):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def summarize_profile(d, workload, kernel):
+    """Read rocprofv3 CSV output under directory d (p_trace, p_fetch, p_write,
+    p_cfetch, p_cwrite from the commands in the profile summary) and print the
+    traffic record of `kernel` (largest launches) plus a kernel-time table."""
+    import csv
+
+    def rows(sub, fname):
+        with open(os.path.join(d, sub, fname)) as f:
+            return list(csv.DictReader(f))
+
+    def scale(sub, counter):
+        vals = [float(r["Counter_Value"]) for r in rows(sub, "run_counter_collection.csv")
+                if "copy" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        return (1 << 30) / 1024.0 / max(vals)  # KiB counted per KiB copied, inverted
+
+    fs, ws_ = scale("p_cfetch", "FETCH_SIZE"), scale("p_cwrite", "WRITE_SIZE")
+    sym = KERNEL_SYMBOLS[kernel]
+
+    def biggest(sub, counter):
+        v = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows(sub, "run_counter_collection.csv")
+             if sym in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        g = max(x for x, _ in v)
+        sel = [c for x, c in v if x == g]
+        return sum(sel) / len(sel) * 1024.0  # bytes
+
+    fetch = biggest("p_fetch", "FETCH_SIZE") * fs
+    write = biggest("p_write", "WRITE_SIZE") * ws_
+    stats = rows("p_trace", "run_kernel_stats.csv")
+    table = []
+    for r in stats:
+        n = r["Name"]
+        if "eiger" not in n:
+            continue
+        short = n.split("::")[-1].split("(")[0] if "::" in n else n
+        table.append((float(r["TotalDurationNs"]), short[:60], int(r["Calls"]), float(r["AverageNs"])))
+    table.sort(reverse=True)
+    rec = {"workload": workload, "kernel": kernel, "sources_sha": sources_digest(kernel),
+           "fetch_bytes_per_launch": int(fetch), "write_bytes_per_launch": int(write),
+           "fetch_scale": round(fs, 4), "write_scale": round(ws_, 4)}
+    print(json.dumps(rec))
+    for tot, name, calls, avg in table[:12]:
+        print(f"| {name} | {calls} | {avg / 1e6:.3f} ms | {tot / 1e6:.3f} ms |")
 
 
 def log(msg):
@@ -119,7 +205,13 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fixed-hash comparison run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--summarize-profile", default="", metavar="DIR",
+                    help="summarize rocprofv3 CSV output under DIR for --kernel and exit (no GPU)")
+    ap.add_argument("--kernel", default="hash_probe")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.workload, args.kernel)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -257,7 +349,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": None,
+                     "traffic": (lambda t: round(t / 1e9, 3) if t else None)(traffic_for(dom, args.workload)),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "alg_bytes_per_launch": int(dom_bytes / max(dom_launches, 1)) if dom_bytes else None,
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 5)},
     }

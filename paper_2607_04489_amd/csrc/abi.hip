@@ -238,7 +238,10 @@ void rule_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out
   // payload width is not part of the statistics: size the slot for 8-byte payloads
   const double slot = b.dtype == EIGER_INT64 ? 32.0 : 16.0;
   const double table = static_cast<double>(hash_slots(static_cast<uint64_t>(b.n), lf)) * slot;
-  if (table <= kHashTableBudget) {
+  // Duplicated build keys share a home slot, so open-addressing clusters grow
+  // with the copies of a key; those builds go to LDS tables after partitioning.
+  const bool duplicated = b.ndv < 0.9 * static_cast<double>(b.n);
+  if (table <= kHashTableBudget && (!duplicated || table <= 64.0 * 1024 * 1024)) {
     out->variant = EIGER_GLOBAL_HASH;
     out->load_factor = lf;
     return;
@@ -246,16 +249,19 @@ void rule_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out
   // Large probes: one pass over the probe side with L2-sized table regions
   // when a region fits at <= 2^10 partitions; otherwise LDS tables.
   const double region = table / std::ldexp(1.0, kCacheMaxBits);
-  if (region <= kCacheRegionBudget) {
+  if (!duplicated && region <= kCacheRegionBudget) {
     out->variant = EIGER_RADIX_CACHE;
     out->load_factor = lf;
     out->radix_bits = cache_bits_for(static_cast<uint64_t>(b.n), b.dtype, lf);
     out->radix_passes = 1;
     return;
   }
+  // LDS tables at a low load factor: short walks matter more than fan-out.
   out->variant = EIGER_RADIX;
-  out->load_factor = lf;
-  out->radix_bits = radix_bits_for(static_cast<uint64_t>(b.n), b.dtype, EIGER_INT64, lf);
+  out->load_factor = 0.25f;
+  // at most two passes of 8 bits (256 buckets each); larger partitions build
+  // their LDS table in several chunks
+  out->radix_bits = std::min(16, radix_bits_for(static_cast<uint64_t>(b.n), b.dtype, EIGER_INT64, out->load_factor));
   out->radix_passes = out->radix_bits > 8 ? 2 : 1;
   (void)p;
 }
