@@ -223,35 +223,19 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     fill = 0;
   }
   if (total > SCAP) {
-    // More matches than the stage holds (duplicated build keys): stage them in
-    // windows of SCAP positions, each thread writing the matches that fall in
-    // the current window, and flush each window whole.
-    for (uint32_t w = 0; w < total; w += SCAP) {
-      const uint32_t wend = total < w + SCAP ? total : w + SCAP;
-      if (off < wend && off + mine > w) {
-        uint32_t pos = off;
+    // More matches than the stage holds (duplicated build keys): each thread
+    // writes its own matches straight into the range reserved for the tile
+    // (measured faster than staging such tiles in windows, which re-walks rows).
+    const uint64_t base = reserve(L, o, total);
+    uint64_t pos = base + off;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-          if (cnt[k] == 1) {
-            if (pos >= w && pos < wend) {
-              L.b[pos - w] = first[k];
-              L.p[pos - w] = r.rid[k];
-            }
-            ++pos;
-          } else if (cnt[k] > 1) {
-            const uint32_t rr = r.rid[k];
-            tab.for_each(r.key[k], [&](uint32_t b) {
-              if (pos >= w && pos < wend) {
-                L.b[pos - w] = b;
-                L.p[pos - w] = rr;
-              }
-              ++pos;
-            });
-          }
-        }
+    for (int k = 0; k < IPT; ++k) {
+      if (cnt[k] == 1) {
+        put_pair(o, pos++, first[k], r.rid[k]);
+      } else if (cnt[k] > 1) {
+        const uint32_t rr = r.rid[k];
+        tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
       }
-      __syncthreads();
-      flush(L, o, wend - w);
     }
     return;
   }
