@@ -185,6 +185,115 @@ int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column
                uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
                int64_t *out_checksum, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- batched joins: many independent joins in one graph launch -----------------
+ * Every join of a batch runs the same path (statistics of the build keys ->
+ * per-join variant choice on the device -> build -> probe -> materialize) with
+ * no host round trip: the work of all joins is captured once into a hipGraph
+ * whose kernels walk flat lists of (join, tile) work items; each launch replays
+ * it. Build keys must be distinct within a join (the usual primary-key side of
+ * a star join); a join whose build keys repeat is flagged and its result is
+ * not valid (run it through eiger_join instead). Keys share one dtype and
+ * payloads one dtype across the batch.
+ */
+typedef struct {
+    const void *build_keys;    /* DEVICE */
+    const void *build_payload; /* DEVICE */
+    const void *probe_keys;    /* DEVICE */
+    const void *probe_payload; /* DEVICE */
+    int64_t n_build;
+    int64_t n_probe;
+} eiger_batch_join;
+
+/* Knobs for the joins whose build side has 2^b .. 2^(b+1)-1 rows (bucket b). */
+typedef struct {
+    float load_factor;   /* hash-table occupancy, (0, 0.9]; default 0.5 */
+    int32_t probe_tile;  /* probe rows per work item, 256..2^20; default 16384 */
+} eiger_batch_tune;
+#define EIGER_BATCH_BUCKETS 33
+#define EIGER_BATCH_DUPLICATE_BUILD 1u /* result flag: the join's build keys repeat */
+
+/* Workspace bytes for a batch (tune: EIGER_BATCH_BUCKETS entries or NULL for defaults). */
+int eiger_join_batch_workspace_size(const eiger_batch_join *joins, int32_t n_joins, int32_t key_dtype,
+                                    int32_t payload_dtype, const eiger_batch_tune *tune, size_t *bytes);
+
+/*
+ * Capture the batch into a graph (nothing runs yet). The pairs of join j go to
+ * out_*_rowid[off_j .. off_j + count_j) with off_j = sum of n_probe over the
+ * joins before j (so each array needs sum(n_probe) entries, DEVICE). The
+ * handle keeps pointers to the caller's descriptors' data, outputs and
+ * workspace; they must stay valid until eiger_join_batch_destroy.
+ */
+int eiger_join_batch_create(const eiger_batch_join *joins, int32_t n_joins, int32_t key_dtype,
+                            int32_t payload_dtype, const eiger_batch_tune *tune, uint32_t *out_build_rowid,
+                            uint32_t *out_probe_rowid, void *ws, size_t ws_bytes, void *stream,
+                            void **handle);
+
+/* Launch the captured graph on `stream` (asynchronous). */
+int eiger_join_batch_launch(void *handle, void *stream);
+
+/* Wait for `stream` and copy per-join results to HOST arrays of n_joins entries
+ * (any may be NULL): pair counts, checksums, variant used, EIGER_BATCH_* flags. */
+int eiger_join_batch_results(void *handle, int64_t *counts, int64_t *checksums, int32_t *variants,
+                             uint32_t *flags, void *stream);
+
+int eiger_join_batch_destroy(void *handle);
+
+/* ---- learned variant selector ---------------------------------------------------
+ * A small MLP (EIGER_SEL_FEATURES -> 64 -> 64 -> EIGER_SEL_CLASSES, ReLU) predicts
+ * log2(join time in ms) of every plan class from 16 features of the two sides'
+ * statistics; EIGER_SEL_LEARNED picks the feasible class with the smallest
+ * prediction. This selector is this library's addition: the paper selects
+ * algorithms from runtime statistics (Section 4) but gives no selection model.
+ * Parameters are one fp32 array: W1[16][64], b1[64], W2[64][64], b2[64],
+ * W3[64][16], b3[16] (row-major, input index first). Training runs on the GPU
+ * with the kernels below (fp32, fixed summation order, no float atomics, so two
+ * runs on the same data give bit-identical parameters).
+ */
+#define EIGER_SEL_FEATURES 16
+#define EIGER_SEL_CLASSES 16
+#define EIGER_MLP_HIDDEN 64
+
+/* Number of fp32 parameters of the selector MLP (6288). */
+int64_t eiger_mlp_param_count(void);
+
+/* Features of a (build, probe) pair of statistics, un-normalized (HOST out[16]).
+ * The list is in the design doc; all are finite for any valid statistics. */
+int eiger_selector_features(const eiger_stats_t *build, const eiger_stats_t *probe, float *out);
+
+/* The plan of class `cls` (0..EIGER_SEL_CLASSES-1) for these statistics.
+ * Returns EIGER_ERR_UNSUPPORTED when the class cannot run them (DIRECT over a
+ * key range above 2^30). */
+int eiger_selector_class_plan(int32_t cls, const eiger_stats_t *build, const eiger_stats_t *probe,
+                              eiger_plan_t *out);
+
+/* Forward pass on the GPU: y[batch][16] = MLP(x[batch][16]). All DEVICE
+ * pointers; x is already normalized. */
+int eiger_mlp_forward(const float *params, const float *x, int32_t batch, float *y, void *stream);
+
+/* Workspace bytes of eiger_mlp_train_step for a batch. */
+size_t eiger_mlp_train_workspace_size(int32_t batch);
+
+/*
+ * One full-batch training step on the GPU: forward, masked mean squared error
+ * L = sum(mask * (y - target)^2) / sum(mask), backward, and an Adam update
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step number `step` >= 1).
+ *  params, adam_m, adam_v  DEVICE, eiger_mlp_param_count() floats each, updated in place
+ *  grads                   DEVICE, eiger_mlp_param_count() floats (gradients on return)
+ *  x, target, mask         DEVICE, batch x 16 floats (mask entries 0 or 1)
+ *  loss                    DEVICE, 1 float: the loss before the update
+ */
+int eiger_mlp_train_step(float *params, float *adam_m, float *adam_v, float *grads, const float *x,
+                         const float *target, const float *mask, int32_t batch, float lr, int32_t step,
+                         float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Install the model used by EIGER_SEL_LEARNED (HOST arrays, copied):
+ * params (eiger_mlp_param_count floats) and the feature normalization
+ * x_norm = (x - mean) / std (16 floats each, std > 0). Process-wide. */
+int eiger_selector_load(const float *params, const float *feat_mean, const float *feat_std);
+
+/* 1 when a model is installed, else 0. */
+int eiger_selector_loaded(void);
+
 /* ---- diagnostics -------------------------------------------------------------- */
 
 /* Message of the calling thread's last failure ("" if none). */

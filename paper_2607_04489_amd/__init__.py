@@ -116,6 +116,31 @@ def lib():
         L.eiger_profile_read.argtypes = [ctypes.POINTER(KernelTime), ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]
         L.eiger_profile_read.restype = ctypes.c_int
+        L.eiger_mlp_param_count.restype = ctypes.c_int64
+        L.eiger_selector_features.argtypes = [ctypes.POINTER(StatsT), ctypes.POINTER(StatsT), vp]
+        L.eiger_selector_features.restype = ctypes.c_int
+        L.eiger_selector_class_plan.argtypes = [i32, ctypes.POINTER(StatsT), ctypes.POINTER(StatsT),
+                                                ctypes.POINTER(PlanT)]
+        L.eiger_selector_class_plan.restype = ctypes.c_int
+        L.eiger_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+        L.eiger_mlp_forward.restype = ctypes.c_int
+        L.eiger_mlp_train_workspace_size.argtypes = [i32]
+        L.eiger_mlp_train_workspace_size.restype = sz
+        L.eiger_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, sz, vp]
+        L.eiger_mlp_train_step.restype = ctypes.c_int
+        L.eiger_selector_load.argtypes = [vp, vp, vp]
+        L.eiger_selector_load.restype = ctypes.c_int
+        L.eiger_selector_loaded.restype = ctypes.c_int
+        L.eiger_join_batch_workspace_size.argtypes = [vp, i32, i32, i32, vp, ctypes.POINTER(sz)]
+        L.eiger_join_batch_workspace_size.restype = ctypes.c_int
+        L.eiger_join_batch_create.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+        L.eiger_join_batch_create.restype = ctypes.c_int
+        L.eiger_join_batch_launch.argtypes = [vp, vp]
+        L.eiger_join_batch_launch.restype = ctypes.c_int
+        L.eiger_join_batch_results.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.eiger_join_batch_results.restype = ctypes.c_int
+        L.eiger_join_batch_destroy.argtypes = [vp]
+        L.eiger_join_batch_destroy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -261,6 +286,183 @@ def join(bk, bp, pk, pp, plan: PlanT, capacity: Optional[int] = None, stream=Non
         rc = run(ob, op, capacity)
     _check(rc, cnt.value)
     return JoinResult(ob[: cnt.value], op[: cnt.value], cnt.value, cs.value)
+
+
+# ---- learned selector -------------------------------------------------------------
+
+SEL_FEATURES, SEL_CLASSES, MLP_HIDDEN = 16, 16, 64
+
+
+def mlp_param_count() -> int:
+    return int(lib().eiger_mlp_param_count())
+
+
+def _fptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def selector_features(build: Stats, probe: Stats):
+    """eiger_selector_features: the 16 raw features (torch float32, host)."""
+    import torch
+    out = torch.zeros(SEL_FEATURES, dtype=torch.float32)
+    _check(lib().eiger_selector_features(ctypes.byref(build.raw), ctypes.byref(probe.raw), _fptr(out)))
+    return out
+
+
+def selector_class_plan(cls: int, build: Stats, probe: Stats) -> Optional[PlanT]:
+    """The plan of selector class `cls`, or None when the class cannot run these inputs."""
+    out = PlanT()
+    rc = lib().eiger_selector_class_plan(int(cls), ctypes.byref(build.raw), ctypes.byref(probe.raw),
+                                         ctypes.byref(out))
+    if rc == EIGER_ERR_UNSUPPORTED:
+        return None
+    _check(rc)
+    return out
+
+
+def mlp_forward(params, x, stream=None):
+    """eiger_mlp_forward on device tensors: params [6288], x [B, 16] -> y [B, 16]."""
+    import torch
+    y = torch.empty(x.shape[0], SEL_CLASSES, dtype=torch.float32, device=x.device)
+    _check(lib().eiger_mlp_forward(_fptr(params), _fptr(x), int(x.shape[0]), _fptr(y), _stream_ptr(stream)))
+    return y
+
+
+class MlpTrainer:
+    """Device state of full-batch Adam training through eiger_mlp_train_step."""
+
+    def __init__(self, params, batch: int):
+        import torch
+        self.params = params.detach().clone().float().contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.ws = _workspace(lib().eiger_mlp_train_workspace_size(int(batch)), params.device)
+        self.batch = int(batch)
+        self.t = 0
+
+    def step(self, x, target, mask, lr: float, stream=None) -> None:
+        assert x.shape[0] == self.batch
+        self.t += 1
+        _check(lib().eiger_mlp_train_step(_fptr(self.params), _fptr(self.m), _fptr(self.v), _fptr(self.grads),
+                                          _fptr(x), _fptr(target), _fptr(mask), self.batch, float(lr), self.t,
+                                          _fptr(self.loss), ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                          _stream_ptr(stream)))
+
+
+def selector_load(params, feat_mean, feat_std) -> None:
+    """eiger_selector_load from host float32 tensors."""
+    import torch
+    p = params.detach().cpu().float().contiguous()
+    m = torch.as_tensor(feat_mean, dtype=torch.float32).contiguous()
+    sd = torch.as_tensor(feat_std, dtype=torch.float32).contiguous()
+    _check(lib().eiger_selector_load(_fptr(p), _fptr(m), _fptr(sd)))
+
+
+def selector_loaded() -> bool:
+    return bool(lib().eiger_selector_loaded())
+
+
+# ---- batched joins -----------------------------------------------------------------
+
+BATCH_BUCKETS = 33
+BATCH_DUPLICATE_BUILD = 1
+
+
+class BatchJoinT(ctypes.Structure):
+    _fields_ = [("build_keys", ctypes.c_void_p), ("build_payload", ctypes.c_void_p),
+                ("probe_keys", ctypes.c_void_p), ("probe_payload", ctypes.c_void_p),
+                ("n_build", ctypes.c_int64), ("n_probe", ctypes.c_int64)]
+
+
+class BatchTuneT(ctypes.Structure):
+    _fields_ = [("load_factor", ctypes.c_float), ("probe_tile", ctypes.c_int32)]
+
+
+def batch_bucket(n_build: int) -> int:
+    """Tuning bucket of a join: floor(log2(n_build)) (0 for n_build <= 1)."""
+    return max(0, int(n_build).bit_length() - 1)
+
+
+class Batch:
+    """A captured batch of joins (eiger_join_batch_*). `joins` is a list of
+    (build_keys, build_payload, probe_keys, probe_payload) device tensors; `tune`
+    maps bucket -> (load_factor, probe_tile). The tensors must outlive the batch."""
+
+    def __init__(self, joins, tune=None, stream=None):
+        import torch
+        self.joins = joins
+        k0, p0 = joins[0][0], joins[0][1]
+        self.kdt, self.pdt = _dtype_code(k0), _dtype_code(p0)
+        arr = (BatchJoinT * len(joins))()
+        for i, (bk, bp, pk, pp) in enumerate(joins):
+            for t in (bk, pk):
+                if _dtype_code(t) != self.kdt:
+                    raise EigerError(EIGER_ERR_DTYPE, "batch: key dtypes differ")
+            for t in (bp, pp):
+                if _dtype_code(t) != self.pdt:
+                    raise EigerError(EIGER_ERR_DTYPE, "batch: payload dtypes differ")
+            arr[i] = BatchJoinT(bk.data_ptr() if bk.numel() else None, bp.data_ptr() if bp.numel() else None,
+                                pk.data_ptr() if pk.numel() else None, pp.data_ptr() if pp.numel() else None,
+                                bk.numel(), pk.numel())
+        self._arr = arr
+        self._tune = None
+        if tune:
+            t = (BatchTuneT * BATCH_BUCKETS)()
+            for b in range(BATCH_BUCKETS):
+                lf, tile = tune.get(b, (0.5, 16384))
+                t[b] = BatchTuneT(float(lf), int(tile))
+            self._tune = t
+        need = ctypes.c_size_t()
+        _check(lib().eiger_join_batch_workspace_size(ctypes.byref(arr), len(joins), self.kdt, self.pdt,
+                                                     ctypes.byref(self._tune) if self._tune else None,
+                                                     ctypes.byref(need)))
+        dev = joins[0][2].device
+        self.offsets = [0]
+        for (_, _, pk, _) in joins:
+            self.offsets.append(self.offsets[-1] + pk.numel())
+        total = max(self.offsets[-1], 1)
+        self.out_b = torch.empty(total, dtype=torch.int32, device=dev)
+        self.out_p = torch.empty(total, dtype=torch.int32, device=dev)
+        self.ws = _workspace(need.value, dev)
+        h = ctypes.c_void_p()
+        _check(lib().eiger_join_batch_create(ctypes.byref(arr), len(joins), self.kdt, self.pdt,
+                                             ctypes.byref(self._tune) if self._tune else None,
+                                             ctypes.c_void_p(self.out_b.data_ptr()),
+                                             ctypes.c_void_p(self.out_p.data_ptr()),
+                                             ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                             _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().eiger_join_batch_launch(self.handle, _stream_ptr(stream)))
+
+    def results(self, stream=None):
+        """(counts, checksums, variants, flags) as numpy arrays (waits for the stream)."""
+        import numpy as np
+        n = len(self.joins)
+        c, s = np.zeros(n, np.int64), np.zeros(n, np.int64)
+        v, f = np.zeros(n, np.int32), np.zeros(n, np.uint32)
+        _check(lib().eiger_join_batch_results(self.handle, c.ctypes.data_as(ctypes.c_void_p),
+                                              s.ctypes.data_as(ctypes.c_void_p), v.ctypes.data_as(ctypes.c_void_p),
+                                              f.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+        return c, s, v, f
+
+    def pairs(self, j, count):
+        lo = self.offsets[j]
+        return self.out_b[lo:lo + count], self.out_p[lo:lo + count]
+
+    def destroy(self):
+        if self.handle:
+            lib().eiger_join_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

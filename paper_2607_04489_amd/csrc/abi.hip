@@ -87,6 +87,9 @@ ProfTable &prof() {
 ProfScope::ProfScope(const char *name, hipStream_t s) : name_(name), stream_(s) {
   ProfTable &t = prof();
   if (!t.on) return;
+  // no timing events inside a stream capture (they would become graph nodes)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   if (hipEventCreate(&start_) != hipSuccess) {
     start_ = nullptr;
     return;
@@ -336,8 +339,11 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
       if (p.variant == EIGER_DIRECT && build->n > 0 && key_range(*build) > kDirectMaxRange)
         return fail(EIGER_ERR_UNSUPPORTED, "eiger_join_plan: DIRECT over a key range above 2^30 values");
       break;
-    case EIGER_SEL_LEARNED:
-      return fail(EIGER_ERR_MODEL, "eiger_join_plan: no learned selector model is loaded");
+    case EIGER_SEL_LEARNED: {
+      const int rc = learned_plan(*build, *probe, &p);
+      if (rc) return rc;
+      break;
+    }
     default:
       return fail(EIGER_ERR_INVALID_ARG, "eiger_join_plan: selector is not an eiger_selector");
   }

@@ -53,4 +53,9 @@ inline size_t slot_bytes(int32_t kdt, int32_t bpdt) {
   return (dtype_size(kdt) + dtype_size(bpdt) + 4 <= 16) ? 16 : 32;
 }
 
+// Learned selector (selector.hip).
+void selector_features(const eiger_stats_t &b, const eiger_stats_t &p, float *out);
+int class_plan(int32_t cls, const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out);
+int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out);
+
 }  // namespace eiger

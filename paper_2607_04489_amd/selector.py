@@ -1,0 +1,215 @@
+"""Measurement, training and evaluation of the learned variant selector.
+
+The selector (an MLP in the C library, EIGER_SEL_LEARNED) predicts log2 of the
+join time of each of the 16 plan classes from 16 features of the two sides'
+statistics. This module produces what it learns from and checks what it gains:
+
+  collect()   time every feasible class on generated instances (exhaustive
+              timing; min over repeats, HIP events around eiger_join), append one
+              JSON line per instance (resumable)
+  train()     full-batch Adam on the GPU through eiger_mlp_train_step (80% split)
+  evaluate()  regret t_chosen / t_best on the held-out 20% for the learned
+              selector, the rule planner and the fixed hash join
+  load_model() / save_model()  the model file (parameters, feature scaling)
+
+Instances come from synth.selector_instance (seeded shapes only).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+import paper_2607_04489_amd as eg
+
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.json")
+DATA_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data", "timings_mi355x.jsonl")
+FIXED_HASH_CLASS = 2  # GLOBAL_HASH at load factor 0.5
+
+
+def _time_join(inp, plan, ws, outs, reps, budget_ms):
+    """Min over `reps` runs of eiger_join (HIP events on the current stream)."""
+    best = math.inf
+    res = None
+    for r in range(reps):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        res = eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, plan,
+                      workspace=ws, outputs=outs)
+        stop.record()
+        stop.synchronize()
+        best = min(best, start.elapsed_time(stop))
+        if best > budget_ms:
+            break
+    return best, res
+
+
+def measure_instance(inp, reps=3):
+    """Exhaustive timing of every feasible class plus the rule plan."""
+    sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
+    feats = eg.selector_features(sb, sp).tolist()
+    plans = [eg.selector_class_plan(c, sb, sp) for c in range(eg.SEL_CLASSES)]
+    rule = eg.join_plan(sb, sp, eg.SEL_RULE)
+    fixed = eg.join_plan(sb, sp, eg.SEL_FIXED_HASH)
+    cnt = eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, fixed, count_only=True)
+    cap = max(cnt.count, 1)
+    outs = (torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device),
+            torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device))
+    need = max(eg.join_workspace_size(p, inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload)
+               for p in plans + [rule] if p is not None)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=inp.probe_keys.device)
+    times = [None] * eg.SEL_CLASSES
+    agree = True
+    best = math.inf
+    for c, p in enumerate(plans):
+        if p is None:
+            continue
+        t, res = _time_join(inp, p, ws, outs, reps, budget_ms=max(20 * best, 5.0))
+        times[c] = t
+        best = min(best, t)
+        agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
+    rule_ms, res = _time_join(inp, rule, ws, outs, reps, budget_ms=math.inf)
+    agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
+    return {"features": feats, "times_ms": times, "rule_ms": rule_ms, "rule_plan": rule.describe(),
+            "pairs": cnt.count, "all_variants_agree": bool(agree)}
+
+
+def collect(path, n_instances, seed=7, reps=3, max_build_log2=22.0, max_probe_log2=25.0, log_every=25,
+            device="cuda:0", time_limit_s=None):
+    """Append one JSON line per instance to `path`, skipping indices already there."""
+    import synth
+    done = set()
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                done.add(json.loads(line)["idx"])
+    t0 = time.time()
+    with open(path, "a") as f:
+        for idx in range(n_instances):
+            if idx in done:
+                continue
+            if time_limit_s and time.time() - t0 > time_limit_s:
+                print(f"time limit reached after {idx} instances", flush=True)
+                break
+            inp = synth.selector_instance(seed, idx, device=device, max_build_log2=max_build_log2,
+                                          max_probe_log2=max_probe_log2)
+            rec = measure_instance(inp, reps)
+            rec.update({"idx": idx, "seed": seed, "params": inp.meta["params"],
+                        "n_build": inp.n_build, "n_probe": inp.n_probe})
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            del inp
+            if idx % log_every == 0:
+                print(f"instance {idx}: best {min(t for t in rec['times_ms'] if t is not None):.3f} ms, "
+                      f"elapsed {time.time() - t0:.0f} s", flush=True)
+
+
+def load_records(path=DATA_PATH):
+    with open(path) as f:
+        return [json.loads(line) for line in f]
+
+
+def split(records, seed=0, train_frac=0.8):
+    order = np.random.default_rng(seed).permutation(len(records))
+    k = int(round(train_frac * len(records)))
+    return [records[i] for i in order[:k]], [records[i] for i in order[k:]]
+
+
+def _arrays(records):
+    X = np.array([r["features"] for r in records], dtype=np.float32)
+    T = np.zeros((len(records), eg.SEL_CLASSES), dtype=np.float32)
+    M = np.zeros_like(T)
+    for i, r in enumerate(records):
+        for c, t in enumerate(r["times_ms"]):
+            if t is not None:
+                T[i, c] = math.log2(max(t, 1e-3))
+                M[i, c] = 1.0
+    return X, T, M
+
+
+def init_params(seed=0):
+    """He-normal weights (std sqrt(2/fan_in)) and zero biases, on the CPU."""
+    g = torch.Generator().manual_seed(seed)
+    parts = []
+    for fan_in, fan_out in ((16, 64), (64, 64), (64, 16)):
+        parts.append(torch.randn(fan_in * fan_out, generator=g) * math.sqrt(2.0 / fan_in))
+        parts.append(torch.zeros(fan_out))
+    return torch.cat(parts).float()
+
+
+def train(records, steps=3000, lr=3e-3, seed=0, device="cuda:0"):
+    """Full-batch Adam with the library's GPU kernels; returns a model dict."""
+    X, T, M = _arrays(records)
+    mean = X.mean(axis=0)
+    std = np.maximum(X.std(axis=0), 1e-3)
+    Xn = (X - mean) / std
+    dev = torch.device(device)
+    tr = eg.MlpTrainer(init_params(seed).to(dev), batch=len(records))
+    x, t, m = (torch.from_numpy(a).to(dev).contiguous() for a in (Xn, T, M))
+    losses = []
+    for s in range(steps):
+        tr.step(x, t, m, lr)
+        if s % 500 == 0 or s == steps - 1:
+            losses.append(float(tr.loss.item()))
+    return {"params": tr.params.cpu(), "mean": mean.astype(np.float32), "std": std.astype(np.float32),
+            "losses": losses, "steps": steps, "lr": lr, "seed": seed}
+
+
+def predict_classes(model, records, device="cuda:0"):
+    """argmin of the predicted log-time over the classes each record measured."""
+    X, _, M = _arrays(records)
+    Xn = (X - model["mean"]) / model["std"]
+    dev = torch.device(device)
+    y = eg.mlp_forward(model["params"].to(dev).contiguous(), torch.from_numpy(Xn.astype(np.float32)).to(dev).contiguous())
+    y = y.cpu().numpy()
+    y[M == 0] = np.inf
+    return y.argmin(axis=1)
+
+
+def evaluate(model, records, device="cuda:0"):
+    """Regret t_chosen / t_best (per instance and summed) of the learned selector,
+    the rule planner and the fixed hash join (GLOBAL_HASH, load factor 0.5)."""
+    pick = predict_classes(model, records, device)
+    best = np.array([min(t for t in r["times_ms"] if t is not None) for r in records])
+    learned = np.array([r["times_ms"][c] for r, c in zip(records, pick)])
+    rule = np.array([r["rule_ms"] for r in records])
+    fixed = np.array([r["times_ms"][FIXED_HASH_CLASS] for r in records])
+
+    def summary(t):
+        ratio = t / best
+        return {"sum_ratio": float(t.sum() / best.sum()), "geomean": float(np.exp(np.log(ratio).mean())),
+                "p50": float(np.percentile(ratio, 50)), "p90": float(np.percentile(ratio, 90)),
+                "p99": float(np.percentile(ratio, 99)), "mean": float(ratio.mean())}
+
+    return {"n": len(records), "learned": summary(learned), "rule": summary(rule), "fixed_hash": summary(fixed),
+            "exhaustive_ms": float(best.sum())}
+
+
+def save_model(model, path=MODEL_PATH, extra=None):
+    doc = {"format": "eiger-selector-mlp-1", "features": eg.SEL_FEATURES, "classes": eg.SEL_CLASSES,
+           "hidden": eg.MLP_HIDDEN, "params": [float(v) for v in model["params"].tolist()],
+           "mean": [float(v) for v in model["mean"]], "std": [float(v) for v in model["std"]],
+           "train": {"steps": model["steps"], "lr": model["lr"], "seed": model["seed"], "losses": model["losses"]}}
+    if extra:
+        doc.update(extra)
+    with open(path, "w") as f:
+        json.dump(doc, f)
+
+
+def load_model(path=MODEL_PATH, install=True):
+    """Read a model file and (by default) install it for EIGER_SEL_LEARNED."""
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("format") != "eiger-selector-mlp-1" or len(doc["params"]) != eg.mlp_param_count():
+        raise eg.EigerError(eg.EIGER_ERR_MODEL, f"{path}: not a selector model of this library")
+    model = {"params": torch.tensor(doc["params"], dtype=torch.float32),
+             "mean": np.array(doc["mean"], dtype=np.float32), "std": np.array(doc["std"], dtype=np.float32),
+             "steps": doc["train"]["steps"], "lr": doc["train"]["lr"], "seed": doc["train"]["seed"],
+             "losses": doc["train"]["losses"]}
+    if install:
+        eg.selector_load(model["params"], model["mean"], model["std"])
+    return model

@@ -285,3 +285,122 @@ __all__ = [
 
 # sanity: the 2^53 scaling of the geometric table matches uniform01's resolution
 assert math.isclose(2.0 ** -53 * (1 << 53), 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Instances for the learned variant selector: a spread of build sizes, key
+# widths, key densities, duplicate factors, probe skew and selectivity.
+
+def _u01(seed, stream, idx):
+    return float(uniform01(rand64(seed, stream, torch.tensor([idx], dtype=torch.int64)))[0])
+
+
+def selector_params(seed: int, idx: int, max_build_log2: float = 22.0, max_probe_log2: float = 25.0) -> dict:
+    """Draw the shape of instance `idx`: build rows 2^U(10, max_build_log2), key
+    width int32/int64, density (distinct/range) 10^U(-6, 0), duplicate factor
+    1 (40%) or U{2..16}, probe Zipf exponent U[0, 1.5], selectivity U[0.01, 1],
+    probe rows = build rows * 2^U(0, 4) capped at 2^max_probe_log2."""
+    u = [_u01(seed, 200 + k, idx) for k in range(8)]
+    n_build = int(round(2.0 ** (10 + u[0] * (max_build_log2 - 10))))
+    wide = u[1] < 0.5
+    density = 10.0 ** (-6.0 * u[2])
+    dup = 1 if u[3] < 0.4 else 2 + int(u[3] * 1e6) % 15
+    zipf_s = 1.5 * u[4]
+    selectivity = 0.01 + 0.99 * u[5]
+    n_probe = int(min(round(n_build * 2.0 ** (4 * u[6])), 2 ** max_probe_log2))
+    return {"n_build": n_build, "wide": wide, "density": density, "dup": dup, "zipf_s": zipf_s,
+            "selectivity": selectivity, "n_probe": n_probe}
+
+
+def selector_instance(seed: int, idx: int, device="cpu", **kw) -> JoinInput:
+    """Build instance `idx` of the selector workload (see selector_params).
+    Distinct build keys are base + i*step + jitter (strictly increasing, so
+    distinct, spread over the chosen range); each is repeated U{1..2*dup-1}
+    times; probe rows take a build key with probability `selectivity` (rank
+    drawn Zipf(s) over the distinct keys through a random rank->key map), else a
+    key beyond the build range."""
+    pr = selector_params(seed, idx, **kw)
+    dev = torch.device(device)
+    dtype = torch.int64 if pr["wide"] else torch.int32
+    n_distinct = max(1, pr["n_build"] // pr["dup"])
+    max_range = (1 << 61) if pr["wide"] else (1 << 30)
+    rng_len = int(min(max_range, max(n_distinct, round(n_distinct / pr["density"]))))
+    step = max(1, rng_len // n_distinct)
+    rng_len = step * n_distinct
+    base = -(rng_len // 2)
+    iv = torch.arange(n_distinct, dtype=torch.int64, device=dev)
+    jitter = torch.remainder(_srl(rand64(seed * 7919 + idx, 1, iv), 1), step) if step > 1 else torch.zeros_like(iv)
+    distinct = base + iv * step + jitter
+    if pr["dup"] > 1:
+        counts = 1 + uniform_below(rand64(seed * 7919 + idx, 2, iv), 2 * pr["dup"] - 1)
+        keys = torch.repeat_interleave(distinct, counts)
+    else:
+        keys = distinct
+    n_build = int(keys.numel())
+    keys = keys[permutation(seed * 7919 + idx, 3, n_build, dev)]
+    ib = torch.arange(n_build, dtype=torch.int64, device=dev)
+    ip = torch.arange(pr["n_probe"], dtype=torch.int64, device=dev)
+    hit = uniform01(rand64(seed * 7919 + idx, 4, ip)) < pr["selectivity"]
+    if pr["zipf_s"] > 0.05 and n_distinct > 1:
+        rank = zipf_ranks(rand64(seed * 7919 + idx, 5, ip), zipf_cdf(n_distinct, pr["zipf_s"]))
+    else:
+        rank = uniform_below(rand64(seed * 7919 + idx, 5, ip), n_distinct)
+    rank_to_key = permutation(seed * 7919 + idx, 6, n_distinct, dev)
+    miss = base + rng_len + torch.remainder(_srl(rand64(seed * 7919 + idx, 7, ip), 1), rng_len)
+    pk = torch.where(hit, distinct[rank_to_key[rank]], miss)
+    pay_b = rand64(seed * 7919 + idx, 8, ib)
+    pay_p = rand64(seed * 7919 + idx, 9, ip)
+    if dtype == torch.int32:
+        pay_b, pay_p = (pay_b >> 40).to(torch.int32), (pay_p >> 40).to(torch.int32)
+    return JoinInput(name=f"selector_{seed}_{idx}", build_keys=keys.to(dtype), build_payload=pay_b,
+                     probe_keys=pk.to(dtype), probe_payload=pay_p, meta={"params": pr})
+
+
+def bij_bits(x: torch.Tensor, bits: int, seed: int) -> torch.Tensor:
+    """A keyed bijection of [0, 2^bits) (bits <= 31): add, odd multiply and
+    xor-shift steps, each invertible mod 2^bits."""
+    m = (1 << bits) - 1
+    k = _stream_base(seed, 8)
+    x = (x + (k & m)) & m
+    x = (x * (((k >> 32) & m) | 1)) & m
+    x = x ^ (x >> (bits // 2))
+    x = (x * 0x2C1B3C6D) & m
+    x = x ^ (x >> (bits // 3 + 1))
+    return x
+
+
+def batched_joins(seed: int, n_joins: int, log2_lo: float = 8.0, log2_hi: float = 18.0, device="cpu"):
+    """Independent unique-key int32 joins of uneven sizes: build rows
+    round(2^U(log2_lo, log2_hi)); probe rows = build rows * U[4, 16]; match rate
+    m ~ U[0.1, 1]. Even-indexed joins are dense: build keys = a shuffle of
+    [b, b + n) and probe keys U[b, b + n/m). Odd-indexed joins are sparse: build
+    keys = 2 * (a keyed bijection of their indices on [0, 2^30)), matching probe
+    rows copy a uniformly drawn build key, the others take odd keys 2v + 1.
+    Payloads U[0, 1000). Returns a list of JoinInput."""
+    dev = torch.device(device)
+    out = []
+    for j in range(n_joins):
+        u = [_u01(seed, 500 + k, j) for k in range(4)]
+        nb = int(round(2.0 ** (log2_lo + u[0] * (log2_hi - log2_lo))))
+        npr = int(round(nb * (4.0 + 12.0 * u[1])))
+        m = 0.1 + 0.9 * u[2]
+        js = seed * 1000003 + j
+        ib = torch.arange(nb, dtype=torch.int64, device=dev)
+        ip = torch.arange(npr, dtype=torch.int64, device=dev)
+        if j % 2 == 0:
+            b = int(u[3] * (1 << 29))
+            bk = b + permutation(js, 1, nb, dev)
+            span = max(1, int(round(nb / m)))
+            pk = b + uniform_below(rand64(js, 2, ip), span)
+        else:
+            bk = 2 * bij_bits(ib, 30, js)
+            hit = uniform01(rand64(js, 3, ip)) < m
+            src = uniform_below(rand64(js, 4, ip), nb)
+            miss = 2 * uniform_below(rand64(js, 5, ip), 1 << 30) + 1
+            pk = torch.where(hit, bk[src], miss)
+        out.append(JoinInput(name=f"batch_{j}", build_keys=bk.to(torch.int32),
+                             build_payload=uniform_below(rand64(js, 6, ib), 1000).to(torch.int32),
+                             probe_keys=pk.to(torch.int32),
+                             probe_payload=uniform_below(rand64(js, 7, ip), 1000).to(torch.int32),
+                             meta={"dense": j % 2 == 0, "match": m}))
+    return out

@@ -5,7 +5,9 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
+import torch
 
 import paper_2607_04489_amd as eg
 
@@ -164,3 +166,29 @@ def test_profile_table_without_gpu(lib):
     eg.profile_enable(True)
     assert eg.profile_read() == {}
     eg.profile_enable(False)
+
+
+def test_selector_host_functions(lib):
+    b, s = stats(10000, 0, 9999, 10000.0), stats(50000, 0, 20000, 20000.0)
+    f = eg.selector_features(b, s)
+    assert f.shape == (16,) and bool(torch.isfinite(f).all())
+    assert abs(float(f[0]) - np.log2(10001)) < 1e-5 and float(f[6]) == 0.0
+    assert eg.mlp_param_count() == 6288
+    for c in range(16):
+        p = eg.selector_class_plan(c, b, s)
+        assert p is not None and 0 <= p.variant <= 3
+    wide = stats(1000, -(1 << 40), 1 << 40, 1000.0, eg.INT64)
+    assert eg.selector_class_plan(0, wide, stats(10, 0, 5, 5.0, eg.INT64)) is None
+    with pytest.raises(eg.EigerError):
+        eg.selector_class_plan(16, b, s)
+
+
+def test_selector_load_rejects_bad_models(lib):
+    import torch as T
+    with pytest.raises(eg.EigerError) as e:
+        eg.selector_load(T.zeros(6288), np.zeros(16), np.zeros(16))
+    assert e.value.code == eg.EIGER_ERR_MODEL
+    bad = T.zeros(6288)
+    bad[5] = float("nan")
+    with pytest.raises(eg.EigerError):
+        eg.selector_load(bad, np.zeros(16), np.ones(16))

@@ -1,0 +1,89 @@
+"""The selector MLP's GPU kernels against the fp64 reference: forward, loss,
+gradients and the Adam update of eiger_mlp_train_step, plus determinism and
+host/device agreement of the learned plan choice."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2607_04489_amd as eg
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(seed, batch):
+    rng = np.random.default_rng(seed)
+    flat = rng.normal(0, 0.3, mlp.N_PARAMS).astype(np.float32)
+    X = rng.normal(0, 1, (batch, 16)).astype(np.float32)
+    T = rng.normal(0, 1, (batch, 16)).astype(np.float32)
+    M = (rng.random((batch, 16)) < 0.7).astype(np.float32)
+    return flat, X, T, M
+
+
+def dev(a, gpu):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(gpu)
+
+
+@pytest.mark.parametrize("batch", [1, 7, 333, 4096])
+def test_forward_matches_reference(gpu, batch):
+    flat, X, _, _ = problem(batch, batch)
+    y = eg.mlp_forward(dev(flat, gpu), dev(X, gpu)).cpu().numpy()
+    ref, _, _ = mlp.forward(flat.astype(np.float64), X.astype(np.float64))
+    assert np.abs(y - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("batch", [5, 300, 2500])
+def test_train_step_matches_reference(gpu, batch):
+    flat, X, T, M = problem(10 + batch, batch)
+    tr = eg.MlpTrainer(dev(flat, gpu), batch)
+    tr.step(dev(X, gpu), dev(T, gpu), dev(M, gpu), lr=1e-3)
+    f64 = flat.astype(np.float64)
+    g_ref = mlp.gradient(f64, X, T, M)
+    g = tr.grads.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+    assert abs(float(tr.loss.item()) - mlp.loss(f64, X, T, M)) <= 1e-5 * mlp.loss(f64, X, T, M)
+    p_ref, _, _ = mlp.adam_step(f64, np.zeros_like(f64), np.zeros_like(f64), g_ref, lr=1e-3, t=1)
+    # a first Adam step moves each parameter by ~lr; where |g| is tiny fp32 rounding
+    # of g changes the sign-like step, so compare only well-determined entries
+    p = tr.params.cpu().numpy().astype(np.float64)
+    sure = np.abs(g_ref) > 1e-3 * np.abs(g_ref).max()
+    assert np.abs(p - p_ref)[sure].max() <= 1e-5
+
+
+def test_training_is_deterministic_and_learns(gpu):
+    flat, X, _, M = problem(3, 512)
+    W = np.random.default_rng(4).normal(size=(16, 16)).astype(np.float32)
+    T = np.tanh(X @ W).astype(np.float32)  # a smooth target the net can fit
+    runs = []
+    for _ in range(2):
+        tr = eg.MlpTrainer(dev(flat * 0.5, gpu), 512)
+        x, t, m = dev(X, gpu), dev(T, gpu), dev(M, gpu)
+        first = None
+        for _ in range(300):
+            tr.step(x, t, m, lr=3e-3)
+            first = first if first is not None else float(tr.loss.item())
+        runs.append((tr.params.cpu().clone(), first, float(tr.loss.item())))
+    assert torch.equal(runs[0][0], runs[1][0])
+    assert runs[0][2] < 0.3 * runs[0][1]
+
+
+def test_learned_plan_matches_device_argmin(gpu):
+    """eiger_join_plan(EIGER_SEL_LEARNED) evaluates the net on the host; its
+    choice must equal the argmin of the device forward over feasible classes."""
+    flat, _, _, _ = problem(5, 1)
+    mean = np.zeros(16, dtype=np.float32)
+    std = np.full(16, 8.0, dtype=np.float32)
+    eg.selector_load(torch.from_numpy(flat), mean, std)
+    assert eg.selector_loaded()
+    import synth
+    for i in range(12):
+        inp = synth.selector_instance(11, i, device=gpu, max_build_log2=14, max_probe_log2=16)
+        sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
+        x = ((eg.selector_features(sb, sp).numpy() - mean) / std).astype(np.float32)
+        y = eg.mlp_forward(dev(flat, gpu), dev(x[None, :], gpu)).cpu().numpy()[0]
+        feas = [c for c in range(16) if eg.selector_class_plan(c, sb, sp) is not None]
+        want = min(feas, key=lambda c: y[c])
+        got = eg.join_plan(sb, sp, eg.SEL_LEARNED)
+        ref = eg.selector_class_plan(want, sb, sp)
+        assert (got.variant, got.radix_bits, got.radix_passes) == (ref.variant, ref.radix_bits, ref.radix_passes)
+        assert abs(got.load_factor - ref.load_factor) < 1e-7
