@@ -175,6 +175,71 @@ def kernel_bytes(plan, inp, count):
     return b
 
 
+def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=18.0, reps=5, autotune=False):
+    """4,096 independent unique-key joins of uneven sizes: one hipGraph launch of
+    the batch (per-join plan on the device) against one eiger_join call sequence
+    per join (rule plan, and fixed GLOBAL_HASH). Returns a summary dict."""
+    import torch
+    import paper_2607_04489_amd as eg
+    import synth
+    from paper_2607_04489_amd import batch as batchmod
+    dev = torch.device("cuda:0")
+    inputs = synth.batched_joins(42, n_joins, log2_lo, log2_hi, device=dev)
+    joins = [(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload) for i in inputs]
+    tune = None
+    if autotune:
+        tune, _ = batchmod.autotune(joins, log=log)
+    elif os.path.exists(batchmod.TUNE_PATH):
+        tune = batchmod.load()
+    b = eg.Batch(joins, tune)
+    b.launch()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record()
+        b.launch()
+        en.record()
+        en.synchronize()
+        times.append(st.elapsed_time(en))
+    counts, sums, variants, flags = b.results()
+    graph_ms = sum(times) / len(times)
+
+    def per_join(selector):
+        ws = torch.empty(1, dtype=torch.uint8, device=dev)
+        cap = max(i.n_probe for i in inputs)
+        outs = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
+        plans = []
+        for i in inputs:
+            sb, sp = eg.stats(i.build_keys), eg.stats(i.probe_keys)
+            plans.append(eg.join_plan(sb, sp, selector))
+        need = max(eg.join_workspace_size(p, i.build_keys, i.build_payload, i.probe_keys, i.probe_payload)
+                   for p, i in zip(plans, inputs))
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = [eg.join(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload, p, workspace=ws, outputs=outs)
+               for p, i in zip(plans, inputs)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, res
+
+    rule_ms, rres = per_join(eg.SEL_RULE)
+    fixed_ms, fres = per_join(eg.SEL_FIXED_HASH)
+    agree = all((r.count, r.checksum) == (int(c), int(s)) for r, c, s in zip(rres, counts, sums))
+    n_probe = sum(i.n_probe for i in inputs)
+    b.destroy()
+    return {"joins": n_joins, "build_rows": sum(i.n_build for i in inputs), "probe_rows": n_probe,
+            "pairs": int(counts.sum()), "graph_ms": round(graph_ms, 3),
+            "graph_probe_tuples_per_s": n_probe / (graph_ms * 1e-3),
+            "per_join_rule_ms": round(rule_ms, 3), "per_join_fixed_hash_ms": round(fixed_ms, 3),
+            "speedup_vs_per_join_rule": round(rule_ms / graph_ms, 2),
+            "speedup_vs_per_join_fixed_hash": round(fixed_ms / graph_ms, 2),
+            "direct_joins": int((variants == eg.DIRECT).sum()), "flagged": int((flags != 0).sum()),
+            "agrees_with_single_joins": bool(agree), "tuned": tune is not None,
+            "workload": (f"{n_joins} unique-key int32 joins, build rows 2^U({log2_lo:g},{log2_hi:g}), probe 4-16x "
+                         f"build, match U[0.1,1], half dense / half sparse keys")}
+
+
 def cpu_baseline(name):
     """The oracle, untuned, on a 1/32-scale instance of the same workload (same
     generator and distributions), single-threaded: statistics of both sides and
@@ -208,9 +273,16 @@ def main():
     ap.add_argument("--summarize-profile", default="", metavar="DIR",
                     help="summarize rocprofv3 CSV output under DIR for --kernel and exit (no GPU)")
     ap.add_argument("--kernel", default="hash_probe")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-joins comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector comparison")
+    ap.add_argument("--autotune", action="store_true", help="autotune the batched graph before timing it")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.workload, args.kernel)
+        return
+    if args.workload == "batched":
+        import torch  # noqa: F401
+        print(json.dumps(bench_batched(autotune=args.autotune)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -326,6 +398,30 @@ def main():
         compare = {"fixed_hash_ms_per_step": round(fms, 4), "speedup_vs_fixed_hash": round(fms / ms, 3)}
         log(f"fixed hash join: {fms:.3f} ms/step")
 
+    learned = None
+    if not args.no_learned and not args.force:
+        from paper_2607_04489_amd import selector as selmod
+        if os.path.exists(selmod.MODEL_PATH):
+            selmod.load_model()
+            lplan = eg.join_plan(sb, sp, eg.SEL_LEARNED)
+            ws_join, outs = prepare(lplan)
+            step(eg.SEL_LEARNED, None)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                _, r3 = step(eg.SEL_LEARNED, None)
+            torch.cuda.synchronize()
+            lms = (time.perf_counter() - t1) / args.steps * 1e3
+            assert (r3.count, r3.checksum) == (res.count, res.checksum)
+            learned = {"plan": lplan.describe(), "ms_per_step": round(lms, 4),
+                       "speedup_vs_fixed_hash": round(compare["fixed_hash_ms_per_step"] / lms, 3) if compare else None}
+            log(f"learned selector: {lplan.describe()} {lms:.3f} ms/step")
+    batched = None
+    if not args.no_batched and args.workload == "sparse_unique64":
+        log("batched joins")
+        del ws_join, outs
+        batched = bench_batched()
+
     out = {
         "metric": METRIC,
         "value": inp.n_probe / (ms * 1e-3),
@@ -356,6 +452,10 @@ def main():
     }
     if compare:
         out["vs_fixed_hash"] = compare
+    if learned:
+        out["learned_selector"] = learned
+    if batched:
+        out["batched"] = batched
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)

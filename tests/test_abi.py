@@ -192,3 +192,43 @@ def test_selector_load_rejects_bad_models(lib):
     bad[5] = float("nan")
     with pytest.raises(eg.EigerError):
         eg.selector_load(bad, np.zeros(16), np.ones(16))
+
+
+def batch_arr(specs):
+    arr = (eg.BatchJoinT * len(specs))()
+    for i, (ptr, nb, npr) in enumerate(specs):
+        arr[i] = eg.BatchJoinT(ptr, ptr, ptr, ptr, nb, npr)
+    return arr
+
+
+def test_batch_host_checks(lib):
+    size = ctypes.c_size_t()
+    ok = batch_arr([(4096, 1000, 8000), (8192, 5, 40), (4096, 0, 10)])
+    assert lib.eiger_join_batch_workspace_size(ok, 3, eg.INT32, eg.INT32, None, ctypes.byref(size)) == 0
+    small = size.value
+    big = batch_arr([(4096, 1 << 20, 1 << 22), (8192, 5, 40), (4096, 0, 10)])
+    assert lib.eiger_join_batch_workspace_size(big, 3, eg.INT32, eg.INT32, None, ctypes.byref(size)) == 0
+    assert size.value > small > 0
+    tune = (eg.BatchTuneT * eg.BATCH_BUCKETS)(*[eg.BatchTuneT(0.25, 4096)] * eg.BATCH_BUCKETS)
+    assert lib.eiger_join_batch_workspace_size(ok, 3, eg.INT32, eg.INT32, ctypes.byref(tune),
+                                               ctypes.byref(size)) == 0
+    assert size.value > small  # a lower load factor needs larger tables
+    assert lib.eiger_join_batch_workspace_size(ok, 0, eg.INT32, eg.INT32, None, ctypes.byref(size)) == eg.EIGER_ERR_INVALID_ARG
+    assert lib.eiger_join_batch_workspace_size(ok, 3, 7, eg.INT32, None, ctypes.byref(size)) == eg.EIGER_ERR_DTYPE
+    assert lib.eiger_join_batch_workspace_size(batch_arr([(None, 10, 10)]), 1, eg.INT32, eg.INT32, None,
+                                               ctypes.byref(size)) == eg.EIGER_ERR_INVALID_ARG
+    assert lib.eiger_join_batch_workspace_size(batch_arr([(4098, 10, 10)]), 1, eg.INT64, eg.INT32, None,
+                                               ctypes.byref(size)) == eg.EIGER_ERR_INVALID_ARG
+    assert lib.eiger_join_batch_workspace_size(batch_arr([(4096, 1 << 33, 10)]), 1, eg.INT32, eg.INT32, None,
+                                               ctypes.byref(size)) == eg.EIGER_ERR_TOO_LARGE
+    h = ctypes.c_void_p()
+    assert lib.eiger_join_batch_create(ok, 3, eg.INT32, eg.INT32, None, None, None, None, 0, None,
+                                       ctypes.byref(h)) == eg.EIGER_ERR_INVALID_ARG  # NULL outputs
+    assert lib.eiger_join_batch_create(ok, 3, eg.INT32, eg.INT32, None, 4096, 4096, None, 0, None,
+                                       ctypes.byref(h)) == eg.EIGER_ERR_WORKSPACE
+    assert lib.eiger_join_batch_launch(None, None) == eg.EIGER_ERR_INVALID_ARG
+    assert lib.eiger_join_batch_destroy(None) == 0
+
+
+def test_batch_bucket():
+    assert [eg.batch_bucket(n) for n in (0, 1, 2, 3, 4, 255, 256, 1 << 20)] == [0, 0, 1, 1, 2, 7, 8, 20]
