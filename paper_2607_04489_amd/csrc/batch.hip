@@ -393,18 +393,28 @@ extern "C" int eiger_join_batch_create(const eiger_batch_join *joins, int32_t n_
   auto *h = new BatchHandle();
   h->n = n_joins;
   h->state = L.state;
-  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  // The caller's stream may be the legacy default stream, which cannot be
+  // captured: record the graph on a private stream (default priority).
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "hipStreamCreateWithFlags");
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cs);
     delete h;
     return hip_fail(e, "hipStreamBeginCapture");
   }
   const bool k64 = key_dtype == EIGER_INT64, p64 = payload_dtype == EIGER_INT64;
-  if (!k64 && !p64) rc = enqueue_batch<int32_t, int32_t>(bp, L, out_build_rowid, out_probe_rowid, s);
-  else if (!k64 && p64) rc = enqueue_batch<int32_t, int64_t>(bp, L, out_build_rowid, out_probe_rowid, s);
-  else if (k64 && !p64) rc = enqueue_batch<int64_t, int32_t>(bp, L, out_build_rowid, out_probe_rowid, s);
-  else rc = enqueue_batch<int64_t, int64_t>(bp, L, out_build_rowid, out_probe_rowid, s);
+  if (!k64 && !p64) rc = enqueue_batch<int32_t, int32_t>(bp, L, out_build_rowid, out_probe_rowid, cs);
+  else if (!k64 && p64) rc = enqueue_batch<int32_t, int64_t>(bp, L, out_build_rowid, out_probe_rowid, cs);
+  else if (k64 && !p64) rc = enqueue_batch<int64_t, int32_t>(bp, L, out_build_rowid, out_probe_rowid, cs);
+  else rc = enqueue_batch<int64_t, int64_t>(bp, L, out_build_rowid, out_probe_rowid, cs);
   hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(s, &g);
+  e = hipStreamEndCapture(cs, &g);
+  (void)hipStreamDestroy(cs);
   if (rc || e != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
     delete h;
