@@ -223,20 +223,46 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     fill = 0;
   }
   if (total > SCAP) {
-    // More matches than the stage holds (duplicated build keys): each thread
-    // writes its own matches straight into the range reserved for the tile
-    // (measured faster than staging such tiles in windows, which re-walks rows).
-    const uint64_t base = reserve(L, o, total);
-    uint64_t pos = base + off;
+    // More matches than the stage holds (duplicated build keys): stage the
+    // tile one row slot k at a time (NT rows per round), so these pairs are
+    // also written contiguously; only a round that alone overflows the stage
+    // writes straight to its reserved range.
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
+      uint32_t tk;
+      const uint32_t ok = block_exclusive_scan<NT>(cnt[k], L.scan, &tk);
+      if (tk == 0) continue;
+      if (fill + tk > SCAP) {
+        flush(L, o, static_cast<uint32_t>(fill));
+        fill = 0;
+      }
+      if (tk > SCAP) {
+        const uint64_t base = reserve(L, o, tk);
+        uint64_t pos = base + ok;
+        if (cnt[k] == 1) {
+          put_pair(o, pos, first[k], r.rid[k]);
+        } else if (cnt[k] > 1) {
+          const uint32_t rr = r.rid[k];
+          tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
+        }
+        continue;
+      }
+      uint32_t pos = static_cast<uint32_t>(fill) + ok;
       if (cnt[k] == 1) {
-        put_pair(o, pos++, first[k], r.rid[k]);
+        L.b[pos] = first[k];
+        L.p[pos] = r.rid[k];
       } else if (cnt[k] > 1) {
         const uint32_t rr = r.rid[k];
-        tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
+        tab.for_each(r.key[k], [&](uint32_t b) {
+          L.b[pos] = b;
+          L.p[pos] = rr;
+          ++pos;
+        });
       }
+      __syncthreads();
+      fill += tk;
     }
+    (void)off;
     return;
   }
   uint32_t pos = static_cast<uint32_t>(fill) + off;
