@@ -20,17 +20,6 @@ constexpr int kNT = 256;
 constexpr int kIPT = 8;
 constexpr int kSCAP = 4096;
 
-// Walks start at the first slot of the 128-byte line that holds the hashed
-// slot, so a probe's walk usually stays inside one cache line (the table is far
-// larger than any cache, and every extra line is an HBM fetch).
-template <typename K, typename PB>
-constexpr uint64_t kLineSlots = 128 / sizeof(Slot<K, PB>);
-
-template <typename K, typename PB>
-__device__ __forceinline__ uint64_t line_home(K key, uint64_t mask) {
-  return fmix64(static_cast<uint64_t>(sext(key))) & mask & ~(kLineSlots<K, PB> - 1);
-}
-
 template <typename K, typename PB>
 struct HashTab {
   static constexpr bool kHashed = true;
@@ -42,7 +31,7 @@ struct HashTab {
 
   __device__ __forceinline__ void init() { unique = dup && *dup == 0; }
   __device__ __forceinline__ uint32_t home(K key) const {
-    return static_cast<uint32_t>(line_home<K, PB>(key, mask));
+    return static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) & mask);
   }
   __device__ __forceinline__ uint32_t next(uint32_t i) const { return static_cast<uint32_t>((i + 1) & mask); }
   __device__ __forceinline__ SlotT load(uint32_t i) const { return slots[i]; }
@@ -80,7 +69,7 @@ __global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ 
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
     const K key = keys[r];
-    uint64_t i = line_home<K, PB>(key, mask);
+    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
     // The table has more slots than rows, so an empty slot is always found.
     for (;;) {
       if (atomicCAS(&slots[i].rowid, kEmpty, static_cast<uint32_t>(r)) == kEmpty) {
