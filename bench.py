@@ -264,7 +264,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="sparse_unique64")
-    ap.add_argument("--selector", default="rule", choices=["rule", "fixed_hash"])
+    ap.add_argument("--selector", default="learned", choices=["learned", "rule", "fixed_hash"],
+                    help="plan selection (learned falls back to rule when no model file exists)")
     ap.add_argument("--force", default="", help="variant,bits,passes,lf (e.g. radix,14,2,0.5)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the fixed-hash comparison run")
@@ -274,7 +275,7 @@ def main():
                     help="summarize rocprofv3 CSV output under DIR for --kernel and exit (no GPU)")
     ap.add_argument("--kernel", default="hash_probe")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-joins comparison")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the rule-planner comparison of the learned plan")
     ap.add_argument("--autotune", action="store_true", help="autotune the batched graph before timing it")
     args = ap.parse_args()
     if args.summarize_profile:
@@ -310,7 +311,13 @@ def main():
     inp = make_workload(args.workload, dev)
     torch.cuda.synchronize()
 
-    sel = {"rule": eg.SEL_RULE, "fixed_hash": eg.SEL_FIXED_HASH}[args.selector]
+    from paper_2607_04489_amd import selector as selmod
+    if args.selector == "learned":
+        if os.path.exists(selmod.MODEL_PATH):
+            selmod.load_model()
+        else:
+            args.selector = "rule"
+    sel = {"learned": eg.SEL_LEARNED, "rule": eg.SEL_RULE, "fixed_hash": eg.SEL_FIXED_HASH}[args.selector]
     forced = None
     if args.force:
         v, bits, passes, lf = args.force.split(",")
@@ -395,27 +402,24 @@ def main():
         torch.cuda.synchronize()
         fms = (time.perf_counter() - t1) / args.steps * 1e3
         assert (r2.count, r2.checksum) == (res.count, res.checksum)
-        compare = {"fixed_hash_ms_per_step": round(fms, 4), "speedup_vs_fixed_hash": round(fms / ms, 3)}
+        compare = {"fixed_hash_ms_per_step": round(fms, 4), "speedup_vs_fixed_hash": round(fms / ms, 3),
+                   "plan": fplan.describe()}
         log(f"fixed hash join: {fms:.3f} ms/step")
 
-    learned = None
-    if not args.no_learned and not args.force:
-        from paper_2607_04489_amd import selector as selmod
-        if os.path.exists(selmod.MODEL_PATH):
-            selmod.load_model()
-            lplan = eg.join_plan(sb, sp, eg.SEL_LEARNED)
-            ws_join, outs = prepare(lplan)
-            step(eg.SEL_LEARNED, None)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                _, r3 = step(eg.SEL_LEARNED, None)
-            torch.cuda.synchronize()
-            lms = (time.perf_counter() - t1) / args.steps * 1e3
-            assert (r3.count, r3.checksum) == (res.count, res.checksum)
-            learned = {"plan": lplan.describe(), "ms_per_step": round(lms, 4),
-                       "speedup_vs_fixed_hash": round(compare["fixed_hash_ms_per_step"] / lms, 3) if compare else None}
-            log(f"learned selector: {lplan.describe()} {lms:.3f} ms/step")
+    rule_cmp = None
+    if not args.no_learned and not args.force and sel == eg.SEL_LEARNED:
+        rplan = eg.join_plan(sb, sp, eg.SEL_RULE)
+        ws_join, outs = prepare(rplan)
+        step(eg.SEL_RULE, None)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, r3 = step(eg.SEL_RULE, None)
+        torch.cuda.synchronize()
+        rms = (time.perf_counter() - t1) / args.steps * 1e3
+        assert (r3.count, r3.checksum) == (res.count, res.checksum)
+        rule_cmp = {"plan": rplan.describe(), "ms_per_step": round(rms, 4), "learned_speedup": round(rms / ms, 3)}
+        log(f"rule planner: {rplan.describe()} {rms:.3f} ms/step")
     batched = None
     if not args.no_batched and args.workload == "sparse_unique64":
         log("batched joins")
@@ -452,8 +456,8 @@ def main():
     }
     if compare:
         out["vs_fixed_hash"] = compare
-    if learned:
-        out["learned_selector"] = learned
+    if rule_cmp:
+        out["vs_rule_planner"] = rule_cmp
     if batched:
         out["batched"] = batched
     if not args.no_cpu_baseline:
