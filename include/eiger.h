@@ -108,7 +108,12 @@ typedef enum {
  *  key_dtype    dtype of both key columns
  *  build_min/max  DIRECT: range of the build keys (from the build statistics)
  *  predicted_out  estimated result size |R||S| / max(ndv_R, ndv_S) (informational)
+ *  flags        EIGER_PLAN_* bits set by eiger_join_plan (informational)
  */
+/* plan.flags: EIGER_SEL_LEARNED met statistics outside its model's training
+ * domain and returned the rule plan instead. */
+#define EIGER_PLAN_RULE_FALLBACK 1u
+
 typedef struct {
     int32_t variant;
     int32_t radix_bits;
@@ -288,8 +293,15 @@ int eiger_mlp_train_step(float *params, float *adam_m, float *adam_v, float *gra
 
 /* Install the model used by EIGER_SEL_LEARNED (HOST arrays, copied):
  * params (eiger_mlp_param_count floats) and the feature normalization
- * x_norm = (x - mean) / std (16 floats each, std > 0). Process-wide. */
-int eiger_selector_load(const float *params, const float *feat_mean, const float *feat_std);
+ * x_norm = (x - mean) / std (16 floats each, std > 0). Process-wide.
+ * feat_lo / feat_hi (16 floats each, lo <= hi, or both NULL) give the box of
+ * raw features the model was trained on: for statistics whose features fall
+ * outside it, EIGER_SEL_LEARNED returns the rule plan (EIGER_SEL_RULE) and sets
+ * EIGER_PLAN_RULE_FALLBACK in plan.flags, since the model's predictions there are
+ * extrapolations. Both NULL: no domain check. One of them NULL:
+ * EIGER_ERR_INVALID_ARG. */
+int eiger_selector_load(const float *params, const float *feat_mean, const float *feat_std,
+                        const float *feat_lo, const float *feat_hi);
 
 /* 1 when a model is installed, else 0. */
 int eiger_selector_loaded(void);

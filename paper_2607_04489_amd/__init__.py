@@ -34,6 +34,7 @@ INT32, INT64 = 0, 1
 DIRECT, GLOBAL_HASH, RADIX, RADIX_CACHE = 0, 1, 2, 3
 VARIANT_NAMES = {DIRECT: "direct", GLOBAL_HASH: "global_hash", RADIX: "radix", RADIX_CACHE: "radix_cache"}
 SEL_RULE, SEL_LEARNED, SEL_FIXED_HASH, SEL_FORCED = 0, 1, 2, 3
+PLAN_RULE_FALLBACK = 1
 HLL_P = 14
 
 
@@ -71,6 +72,8 @@ class PlanT(ctypes.Structure):
             d["radix_bits"] = int(self.radix_bits)
         if self.variant == RADIX:
             d["radix_passes"] = int(self.radix_passes)
+        if self.flags & PLAN_RULE_FALLBACK:
+            d["rule_fallback"] = True
         return d
 
 
@@ -128,7 +131,7 @@ def lib():
         L.eiger_mlp_train_workspace_size.restype = sz
         L.eiger_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, vp, vp, sz, vp]
         L.eiger_mlp_train_step.restype = ctypes.c_int
-        L.eiger_selector_load.argtypes = [vp, vp, vp]
+        L.eiger_selector_load.argtypes = [vp, vp, vp, vp, vp]
         L.eiger_selector_load.restype = ctypes.c_int
         L.eiger_selector_loaded.restype = ctypes.c_int
         L.eiger_join_batch_workspace_size.argtypes = [vp, i32, i32, i32, vp, ctypes.POINTER(sz)]
@@ -351,13 +354,17 @@ class MlpTrainer:
                                           _stream_ptr(stream)))
 
 
-def selector_load(params, feat_mean, feat_std) -> None:
-    """eiger_selector_load from host float32 tensors."""
+def selector_load(params, feat_mean, feat_std, feat_lo=None, feat_hi=None) -> None:
+    """eiger_selector_load from host float32 tensors; feat_lo/feat_hi (raw
+    feature bounds of the training data) turn on the domain check."""
     import torch
     p = params.detach().cpu().float().contiguous()
     m = torch.as_tensor(feat_mean, dtype=torch.float32).contiguous()
     sd = torch.as_tensor(feat_std, dtype=torch.float32).contiguous()
-    _check(lib().eiger_selector_load(_fptr(p), _fptr(m), _fptr(sd)))
+    lo = None if feat_lo is None else torch.as_tensor(feat_lo, dtype=torch.float32).contiguous()
+    hi = None if feat_hi is None else torch.as_tensor(feat_hi, dtype=torch.float32).contiguous()
+    _check(lib().eiger_selector_load(_fptr(p), _fptr(m), _fptr(sd), None if lo is None else _fptr(lo),
+                                     None if hi is None else _fptr(hi)))
 
 
 def selector_loaded() -> bool:

@@ -340,8 +340,13 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
         return fail(EIGER_ERR_UNSUPPORTED, "eiger_join_plan: DIRECT over a key range above 2^30 values");
       break;
     case EIGER_SEL_LEARNED: {
-      const int rc = learned_plan(*build, *probe, &p);
+      bool in_domain = true;
+      const int rc = learned_plan(*build, *probe, &p, &in_domain);
       if (rc) return rc;
+      if (!in_domain) {
+        rule_plan(*build, *probe, &p);
+        p.flags |= EIGER_PLAN_RULE_FALLBACK;
+      }
       break;
     }
     default:

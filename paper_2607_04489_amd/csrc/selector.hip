@@ -34,7 +34,8 @@ double range_of(const eiger_stats_t &s) {
 struct Model {
   std::mutex mu;
   bool loaded = false;
-  std::vector<float> params, mean, stdv;
+  bool has_domain = false;
+  std::vector<float> params, mean, stdv, lo, hi;
 };
 
 Model &model() {
@@ -118,18 +119,27 @@ int class_plan(int32_t cls, const eiger_stats_t &b, const eiger_stats_t &p, eige
   return EIGER_OK;
 }
 
-int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out) {
+int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out, bool *in_domain) {
   Model &m = model();
-  std::vector<float> P, mean, stdv;
+  std::vector<float> P, mean, stdv, lo, hi;
+  bool has_domain;
   {
     std::lock_guard<std::mutex> g(m.mu);
     if (!m.loaded) return fail(EIGER_ERR_MODEL, "eiger_join_plan: no learned selector model is loaded");
     P = m.params;
     mean = m.mean;
     stdv = m.stdv;
+    lo = m.lo;
+    hi = m.hi;
+    has_domain = m.has_domain;
   }
   float x[kIn], y[kOut];
   selector_features(b, p, x);
+  *in_domain = true;
+  if (has_domain)
+    for (int i = 0; i < kIn; ++i)
+      if (!(x[i] >= lo[i] && x[i] <= hi[i])) *in_domain = false;
+  if (!*in_domain) return EIGER_OK;
   for (int i = 0; i < kIn; ++i) x[i] = (x[i] - mean[i]) / stdv[i];
   host_forward(P.data(), x, y);
   int best = -1;
@@ -160,8 +170,15 @@ extern "C" int eiger_selector_class_plan(int32_t cls, const eiger_stats_t *build
   return class_plan(cls, *build, *probe, out);
 }
 
-extern "C" int eiger_selector_load(const float *params, const float *feat_mean, const float *feat_std) {
+extern "C" int eiger_selector_load(const float *params, const float *feat_mean, const float *feat_std,
+                                   const float *feat_lo, const float *feat_hi) {
   if (!params || !feat_mean || !feat_std) return fail(EIGER_ERR_INVALID_ARG, "eiger_selector_load: NULL argument");
+  if (!feat_lo != !feat_hi)
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_selector_load: give both feature bounds or neither");
+  if (feat_lo)
+    for (int i = 0; i < kIn; ++i)
+      if (!(feat_lo[i] <= feat_hi[i]))
+        return fail(EIGER_ERR_MODEL, "eiger_selector_load: feature bounds need lo <= hi (and no NaN)");
   for (int i = 0; i < kIn; ++i)
     if (!(feat_std[i] > 0.f) || !std::isfinite(feat_mean[i]))
       return fail(EIGER_ERR_MODEL, "eiger_selector_load: feature std must be > 0 and mean finite");
@@ -172,6 +189,14 @@ extern "C" int eiger_selector_load(const float *params, const float *feat_mean, 
   m.params.assign(params, params + kParams);
   m.mean.assign(feat_mean, feat_mean + kIn);
   m.stdv.assign(feat_std, feat_std + kIn);
+  m.has_domain = feat_lo != nullptr;
+  if (feat_lo) {
+    m.lo.assign(feat_lo, feat_lo + kIn);
+    m.hi.assign(feat_hi, feat_hi + kIn);
+  } else {
+    m.lo.clear();
+    m.hi.clear();
+  }
   m.loaded = true;
   return EIGER_OK;
 }

@@ -56,6 +56,8 @@ inline size_t slot_bytes(int32_t kdt, int32_t bpdt) {
 // Learned selector (selector.hip).
 void selector_features(const eiger_stats_t &b, const eiger_stats_t &p, float *out);
 int class_plan(int32_t cls, const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out);
-int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out);
+// Sets *in_domain = false (and leaves *out alone) when the features lie
+// outside the installed model's training box.
+int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out, bool *in_domain);
 
 }  // namespace eiger

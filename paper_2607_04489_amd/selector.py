@@ -28,6 +28,11 @@ import paper_2607_04489_amd as eg
 
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_model.json")
 DATA_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data", "timings_mi355x.jsonl")
+# family 2 (synth.selector_params): larger builds, wider probe ratios, misses
+# inside the build range, full 64-bit key layouts
+DATA_PATH_WIDE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data",
+                              "timings_mi355x_wide.jsonl")
+DATA_PATHS = (DATA_PATH, DATA_PATH_WIDE)
 FIXED_HASH_CLASS = 2  # GLOBAL_HASH at load factor 0.5
 
 
@@ -48,7 +53,7 @@ def _time_join(inp, plan, ws, outs, reps, budget_ms):
     return best, res
 
 
-def measure_instance(inp, reps=3):
+def measure_instance(inp, reps=3, max_pairs=1 << 32):
     """Exhaustive timing of every feasible class plus the rule plan."""
     sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
     feats = eg.selector_features(sb, sp).tolist()
@@ -56,6 +61,10 @@ def measure_instance(inp, reps=3):
     rule = eg.join_plan(sb, sp, eg.SEL_RULE)
     fixed = eg.join_plan(sb, sp, eg.SEL_FIXED_HASH)
     cnt = eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, fixed, count_only=True)
+    if cnt.count > max_pairs:
+        return {"features": feats, "times_ms": [None] * eg.SEL_CLASSES, "rule_ms": None,
+                "rule_plan": rule.describe(), "pairs": cnt.count, "all_variants_agree": None,
+                "skipped": f"result above {max_pairs} pairs"}
     cap = max(cnt.count, 1)
     outs = (torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device),
             torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device))
@@ -79,38 +88,56 @@ def measure_instance(inp, reps=3):
 
 
 def collect(path, n_instances, seed=7, reps=3, max_build_log2=22.0, max_probe_log2=25.0, log_every=25,
-            device="cuda:0", time_limit_s=None):
-    """Append one JSON line per instance to `path`, skipping indices already there."""
+            device="cuda:0", time_limit_s=None, family=1, min_build_log2=10.0, max_pairs=1 << 32):
+    """Append one JSON line per instance to `path`, skipping (seed, idx) pairs
+    already there. Instances whose result exceeds `max_pairs` pairs are logged
+    as skipped (no timings) rather than materialized."""
     import synth
     done = set()
     if os.path.exists(path):
         with open(path) as f:
             for line in f:
-                done.add(json.loads(line)["idx"])
+                r = json.loads(line)
+                done.add((r["seed"], r["idx"]))
     t0 = time.time()
+    kw = dict(max_build_log2=max_build_log2, max_probe_log2=max_probe_log2)
+    if family != 1 or min_build_log2 != 10.0:
+        kw.update(family=family, min_build_log2=min_build_log2)
     with open(path, "a") as f:
         for idx in range(n_instances):
-            if idx in done:
+            if (seed, idx) in done:
                 continue
             if time_limit_s and time.time() - t0 > time_limit_s:
-                print(f"time limit reached after {idx} instances", flush=True)
+                print(f"time limit reached at instance {idx}", flush=True)
                 break
-            inp = synth.selector_instance(seed, idx, device=device, max_build_log2=max_build_log2,
-                                          max_probe_log2=max_probe_log2)
-            rec = measure_instance(inp, reps)
+            inp = synth.selector_instance(seed, idx, device=device, **kw)
+            rec = measure_instance(inp, reps, max_pairs=max_pairs)
             rec.update({"idx": idx, "seed": seed, "params": inp.meta["params"],
                         "n_build": inp.n_build, "n_probe": inp.n_probe})
             f.write(json.dumps(rec) + "\n")
             f.flush()
             del inp
+            torch.cuda.empty_cache()
             if idx % log_every == 0:
-                print(f"instance {idx}: best {min(t for t in rec['times_ms'] if t is not None):.3f} ms, "
-                      f"elapsed {time.time() - t0:.0f} s", flush=True)
+                ts = [t for t in rec["times_ms"] if t is not None]
+                best = f"{min(ts):.3f} ms" if ts else "skipped"
+                print(f"instance {idx}: best {best}, elapsed {time.time() - t0:.0f} s", flush=True)
 
 
-def load_records(path=DATA_PATH):
-    with open(path) as f:
-        return [json.loads(line) for line in f]
+def load_records(paths=None):
+    """Timed instances of every data file (skipped instances left out)."""
+    if paths is None:
+        paths = [p for p in DATA_PATHS if os.path.exists(p)]
+    elif isinstance(paths, str):
+        paths = [paths]
+    out = []
+    for path in paths:
+        with open(path) as f:
+            for line in f:
+                r = json.loads(line)
+                if not r.get("skipped"):
+                    out.append(r)
+    return out
 
 
 def split(records, seed=0, train_frac=0.8):
@@ -156,6 +183,7 @@ def train(records, steps=3000, lr=3e-3, seed=0, device="cuda:0"):
         if s % 500 == 0 or s == steps - 1:
             losses.append(float(tr.loss.item()))
     return {"params": tr.params.cpu(), "mean": mean.astype(np.float32), "std": std.astype(np.float32),
+            "lo": X.min(axis=0), "hi": X.max(axis=0),
             "losses": losses, "steps": steps, "lr": lr, "seed": seed}
 
 
@@ -175,8 +203,13 @@ def evaluate(model, records, device="cuda:0"):
     the rule planner and the fixed hash join (GLOBAL_HASH, load factor 0.5)."""
     pick = predict_classes(model, records, device)
     best = np.array([min(t for t in r["times_ms"] if t is not None) for r in records])
-    learned = np.array([r["times_ms"][c] for r, c in zip(records, pick)])
     rule = np.array([r["rule_ms"] for r in records])
+    # outside the training box the library returns the rule plan
+    X = np.array([r["features"] for r in records], dtype=np.float32)
+    ood = np.zeros(len(records), dtype=bool)
+    if model.get("lo") is not None:
+        ood = ((X < model["lo"]) | (X > model["hi"])).any(axis=1)
+    learned = np.array([rr if o else r["times_ms"][c] for r, c, rr, o in zip(records, pick, rule, ood)])
     fixed = np.array([r["times_ms"][FIXED_HASH_CLASS] for r in records])
 
     def summary(t):
@@ -185,7 +218,8 @@ def evaluate(model, records, device="cuda:0"):
                 "p50": float(np.percentile(ratio, 50)), "p90": float(np.percentile(ratio, 90)),
                 "p99": float(np.percentile(ratio, 99)), "mean": float(ratio.mean())}
 
-    return {"n": len(records), "learned": summary(learned), "rule": summary(rule), "fixed_hash": summary(fixed),
+    return {"n": len(records), "out_of_domain": int(ood.sum()), "learned": summary(learned), "rule": summary(rule),
+            "fixed_hash": summary(fixed),
             "exhaustive_ms": float(best.sum())}
 
 
@@ -193,6 +227,7 @@ def save_model(model, path=MODEL_PATH, extra=None):
     doc = {"format": "eiger-selector-mlp-1", "features": eg.SEL_FEATURES, "classes": eg.SEL_CLASSES,
            "hidden": eg.MLP_HIDDEN, "params": [float(v) for v in model["params"].tolist()],
            "mean": [float(v) for v in model["mean"]], "std": [float(v) for v in model["std"]],
+           "domain": {"lo": [float(v) for v in model["lo"]], "hi": [float(v) for v in model["hi"]]},
            "train": {"steps": model["steps"], "lr": model["lr"], "seed": model["seed"], "losses": model["losses"]}}
     if extra:
         doc.update(extra)
@@ -209,7 +244,9 @@ def load_model(path=MODEL_PATH, install=True):
     model = {"params": torch.tensor(doc["params"], dtype=torch.float32),
              "mean": np.array(doc["mean"], dtype=np.float32), "std": np.array(doc["std"], dtype=np.float32),
              "steps": doc["train"]["steps"], "lr": doc["train"]["lr"], "seed": doc["train"]["seed"],
-             "losses": doc["train"]["losses"]}
+             "losses": doc["train"]["losses"],
+             "lo": np.array(doc["domain"]["lo"], dtype=np.float32) if "domain" in doc else None,
+             "hi": np.array(doc["domain"]["hi"], dtype=np.float32) if "domain" in doc else None}
     if install:
-        eg.selector_load(model["params"], model["mean"], model["std"])
+        eg.selector_load(model["params"], model["mean"], model["std"], model["lo"], model["hi"])
     return model

@@ -295,61 +295,100 @@ def _u01(seed, stream, idx):
     return float(uniform01(rand64(seed, stream, torch.tensor([idx], dtype=torch.int64)))[0])
 
 
-def selector_params(seed: int, idx: int, max_build_log2: float = 22.0, max_probe_log2: float = 25.0) -> dict:
-    """Draw the shape of instance `idx`: build rows 2^U(10, max_build_log2), key
-    width int32/int64, density (distinct/range) 10^U(-6, 0), duplicate factor
-    1 (40%) or U{2..16}, probe Zipf exponent U[0, 1.5], selectivity U[0.01, 1],
-    probe rows = build rows * 2^U(0, 4) capped at 2^max_probe_log2."""
+def selector_params(seed: int, idx: int, max_build_log2: float = 22.0, max_probe_log2: float = 25.0,
+                    family: int = 1, min_build_log2: float = 10.0) -> dict:
+    """Draw the shape of instance `idx`.
+
+    Family 1: build rows 2^U(min_build_log2, max_build_log2), key width
+    int32/int64, density (distinct/range) 10^U(-6, 0), duplicate factor 1 (40%)
+    or U{2..16}, probe Zipf exponent U[0, 1.5], selectivity U[0.01, 1], probe
+    rows = build rows * 2^U(0, 4) capped at 2^max_probe_log2; rows that miss take
+    keys above the build range.
+
+    Family 2 widens what family 1 leaves out: probe rows = build rows * 2^U(0, 5);
+    half of the instances put missing keys into the gaps between build keys (so
+    the probe range equals the build range) instead of above it; and 40% of the
+    int64 instances spread their keys over the whole 64-bit range."""
     u = [_u01(seed, 200 + k, idx) for k in range(8)]
-    n_build = int(round(2.0 ** (10 + u[0] * (max_build_log2 - 10))))
+    n_build = int(round(2.0 ** (min_build_log2 + u[0] * (max_build_log2 - min_build_log2))))
     wide = u[1] < 0.5
     density = 10.0 ** (-6.0 * u[2])
     dup = 1 if u[3] < 0.4 else 2 + int(u[3] * 1e6) % 15
     zipf_s = 1.5 * u[4]
     selectivity = 0.01 + 0.99 * u[5]
-    n_probe = int(min(round(n_build * 2.0 ** (4 * u[6])), 2 ** max_probe_log2))
-    return {"n_build": n_build, "wide": wide, "density": density, "dup": dup, "zipf_s": zipf_s,
-            "selectivity": selectivity, "n_probe": n_probe}
+    mult_log2 = 4.0 if family == 1 else 5.0
+    n_probe = int(min(round(n_build * 2.0 ** (mult_log2 * u[6])), 2 ** max_probe_log2))
+    pr = {"n_build": n_build, "wide": wide, "density": density, "dup": dup, "zipf_s": zipf_s,
+          "selectivity": selectivity, "n_probe": n_probe}
+    if family != 1:
+        u8 = _u01(seed, 208, idx)
+        pr["family"] = family
+        pr["layout"] = "full64" if (wide and u8 < 0.4) else "spread"
+        pr["miss"] = "inside" if (pr["layout"] == "full64" or u[7] >= 0.5) else "above"
+    return pr
 
 
 def selector_instance(seed: int, idx: int, device="cpu", **kw) -> JoinInput:
     """Build instance `idx` of the selector workload (see selector_params).
-    Distinct build keys are base + i*step + jitter (strictly increasing, so
-    distinct, spread over the chosen range); each is repeated U{1..2*dup-1}
-    times; probe rows take a build key with probability `selectivity` (rank
-    drawn Zipf(s) over the distinct keys through a random rank->key map), else a
-    key beyond the build range."""
+
+    Layout "spread" (family 1 always): distinct build keys are
+    base + i*step + jitter_i with jitter_i in [0, step) (strictly increasing, so
+    distinct, spread over the chosen range). Layout "full64": distinct build
+    keys are mix64(c + i), a bijection, so they are distinct and spread over
+    all 64-bit values. Each distinct key is repeated U{1..2*dup-1} times. Probe
+    rows take a build key with probability `selectivity` (rank drawn Zipf(s)
+    over the distinct keys through a random rank->key map), else a key that no
+    build row holds: above the build range ("above"), inside one of its gaps
+    (offset != jitter_i in the i-th step, "inside"), or mix64(c + n_distinct + j)
+    for the full64 layout."""
     pr = selector_params(seed, idx, **kw)
     dev = torch.device(device)
     dtype = torch.int64 if pr["wide"] else torch.int32
     n_distinct = max(1, pr["n_build"] // pr["dup"])
-    max_range = (1 << 61) if pr["wide"] else (1 << 30)
-    rng_len = int(min(max_range, max(n_distinct, round(n_distinct / pr["density"]))))
-    step = max(1, rng_len // n_distinct)
-    rng_len = step * n_distinct
-    base = -(rng_len // 2)
+    sid = seed * 7919 + idx
     iv = torch.arange(n_distinct, dtype=torch.int64, device=dev)
-    jitter = torch.remainder(_srl(rand64(seed * 7919 + idx, 1, iv), 1), step) if step > 1 else torch.zeros_like(iv)
-    distinct = base + iv * step + jitter
+    layout = pr.get("layout", "spread")
+    if layout == "full64":
+        c = _s64(_stream_base(sid, 10))
+        distinct = mix64(iv + c)
+        step, base, rng_len = 0, 0, 0
+    else:
+        max_range = (1 << 61) if pr["wide"] else (1 << 30)
+        rng_len = int(min(max_range, max(n_distinct, round(n_distinct / pr["density"]))))
+        step = max(1, rng_len // n_distinct)
+        rng_len = step * n_distinct
+        base = -(rng_len // 2)
+        jitter = torch.remainder(_srl(rand64(sid, 1, iv), 1), step) if step > 1 else torch.zeros_like(iv)
+        distinct = base + iv * step + jitter
     if pr["dup"] > 1:
-        counts = 1 + uniform_below(rand64(seed * 7919 + idx, 2, iv), 2 * pr["dup"] - 1)
+        counts = 1 + uniform_below(rand64(sid, 2, iv), 2 * pr["dup"] - 1)
         keys = torch.repeat_interleave(distinct, counts)
     else:
         keys = distinct
     n_build = int(keys.numel())
-    keys = keys[permutation(seed * 7919 + idx, 3, n_build, dev)]
+    keys = keys[permutation(sid, 3, n_build, dev)]
     ib = torch.arange(n_build, dtype=torch.int64, device=dev)
     ip = torch.arange(pr["n_probe"], dtype=torch.int64, device=dev)
-    hit = uniform01(rand64(seed * 7919 + idx, 4, ip)) < pr["selectivity"]
+    hit = uniform01(rand64(sid, 4, ip)) < pr["selectivity"]
     if pr["zipf_s"] > 0.05 and n_distinct > 1:
-        rank = zipf_ranks(rand64(seed * 7919 + idx, 5, ip), zipf_cdf(n_distinct, pr["zipf_s"]))
+        rank = zipf_ranks(rand64(sid, 5, ip), zipf_cdf(n_distinct, pr["zipf_s"]))
     else:
-        rank = uniform_below(rand64(seed * 7919 + idx, 5, ip), n_distinct)
-    rank_to_key = permutation(seed * 7919 + idx, 6, n_distinct, dev)
-    miss = base + rng_len + torch.remainder(_srl(rand64(seed * 7919 + idx, 7, ip), 1), rng_len)
+        rank = uniform_below(rand64(sid, 5, ip), n_distinct)
+    rank_to_key = permutation(sid, 6, n_distinct, dev)
+    r7 = rand64(sid, 7, ip)
+    miss_mode = pr.get("miss", "above")
+    if layout == "full64":
+        miss = mix64(c + n_distinct + _srl(r7, 24))
+    elif miss_mode == "inside" and step > 1:
+        slot = uniform_below(r7, n_distinct)
+        jit = jitter[slot]
+        off = torch.remainder(jit + 1 + torch.remainder(_srl(rand64(sid, 11, ip), 1), step - 1), step)
+        miss = base + slot * step + off
+    else:
+        miss = base + rng_len + torch.remainder(_srl(r7, 1), rng_len)
     pk = torch.where(hit, distinct[rank_to_key[rank]], miss)
-    pay_b = rand64(seed * 7919 + idx, 8, ib)
-    pay_p = rand64(seed * 7919 + idx, 9, ip)
+    pay_b = rand64(sid, 8, ib)
+    pay_p = rand64(sid, 9, ip)
     if dtype == torch.int32:
         pay_b, pay_p = (pay_b >> 40).to(torch.int32), (pay_p >> 40).to(torch.int32)
     return JoinInput(name=f"selector_{seed}_{idx}", build_keys=keys.to(dtype), build_payload=pay_b,

@@ -194,6 +194,35 @@ def test_selector_load_rejects_bad_models(lib):
         eg.selector_load(bad, np.zeros(16), np.ones(16))
 
 
+def test_selector_domain_guard_falls_back_to_rule(lib):
+    """Outside the installed model's training box EIGER_SEL_LEARNED returns the
+    rule plan with EIGER_PLAN_RULE_FALLBACK; inside it returns the model's class."""
+    import torch as T
+    params = T.zeros(6288)
+    params[6272:] = 5.0
+    params[6272 + 1] = -1.0  # the output bias alone ranks class 1 (GLOBAL_HASH lf 0.25) first
+    b, s = stats(1 << 20, -(1 << 40), 1 << 40, float(1 << 20), eg.INT64), \
+        stats(1 << 22, -(1 << 40), 1 << 40, float(1 << 20), eg.INT64)
+    f = eg.selector_features(b, s).numpy()
+    eg.selector_load(params, np.zeros(16), np.ones(16), f - 0.5, f + 0.5)
+    inside = plan(b, s, eg.SEL_LEARNED)
+    assert (inside.variant, round(inside.load_factor, 3), inside.flags) == (eg.GLOBAL_HASH, 0.25, 0)
+    big = stats(1 << 26, -(1 << 40), 1 << 40, float(1 << 26), eg.INT64)
+    out = plan(big, s, eg.SEL_LEARNED)
+    rule = plan(big, s, eg.SEL_RULE)
+    assert out.flags == eg.PLAN_RULE_FALLBACK and rule.flags == 0
+    assert out.describe() == dict(rule.describe(), rule_fallback=True)
+    # no box: the model decides everywhere
+    eg.selector_load(params, np.zeros(16), np.ones(16))
+    assert plan(big, s, eg.SEL_LEARNED).flags == 0
+    with pytest.raises(eg.EigerError) as e:
+        eg.selector_load(params, np.zeros(16), np.ones(16), f + 1.0, f)
+    assert e.value.code == eg.EIGER_ERR_MODEL
+    lo = T.as_tensor(f).contiguous()
+    assert lib.eiger_selector_load(eg._fptr(params), eg._fptr(T.zeros(16)), eg._fptr(T.ones(16)),
+                                   eg._fptr(lo), None) == eg.EIGER_ERR_INVALID_ARG
+
+
 def batch_arr(specs):
     arr = (eg.BatchJoinT * len(specs))()
     for i, (ptr, nb, npr) in enumerate(specs):

@@ -38,6 +38,14 @@ def test_committed_model_is_the_trained_one(trained):
     committed = selector.load_model(install=False)
     assert torch.equal(committed["params"], model["params"].cpu())
     assert np.array_equal(committed["mean"], model["mean"])
+    assert np.array_equal(committed["lo"], model["lo"]) and np.array_equal(committed["hi"], model["hi"])
+
+
+def test_training_instances_lie_inside_the_domain(trained):
+    """The library's domain check keeps every training instance on the model."""
+    _, train, _, model = trained
+    X = np.array([r["features"] for r in train], dtype=np.float32)
+    assert ((X >= model["lo"]) & (X <= model["hi"])).all()
 
 
 def test_training_is_deterministic(trained):

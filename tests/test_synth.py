@@ -64,6 +64,50 @@ def test_bij31_is_injective_on_a_range():
     assert torch.unique(x).numel() == 1 << 20
 
 
+def test_selector_family1_params_match_stored_records():
+    """Family 1 draws are frozen: the collected timings refer to them by (seed, idx)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2607_04489_amd", "selector_data",
+                        "timings_mi355x.jsonl")
+    with open(path) as f:
+        recs = [json.loads(next(f)) for _ in range(40)]
+    for r in recs:
+        assert synth.selector_params(r["seed"], r["idx"]) == r["params"]
+
+
+@pytest.mark.parametrize("idx", range(24))
+def test_selector_family2_hits_and_misses_exact(idx):
+    """Rows drawn as hits hold a build key; rows drawn as misses hold none, for
+    every layout (gaps inside the range, above it, full 64-bit keys)."""
+    kw = dict(max_build_log2=12, min_build_log2=9, max_probe_log2=14, family=2)
+    inp = synth.selector_instance(8, idx, **kw)
+    pr = inp.meta["params"]
+    sid = 8 * 7919 + idx
+    ip = torch.arange(pr["n_probe"], dtype=torch.int64)
+    hit = (synth.uniform01(synth.rand64(sid, 4, ip)) < pr["selectivity"]).numpy()
+    bk = inp.build_keys.numpy().astype(np.int64)
+    pk = inp.probe_keys.numpy().astype(np.int64)
+    inb = np.isin(pk, bk)
+    assert inb[hit].all() and not inb[~hit].any()
+    nd = np.unique(bk).size
+    if pr["layout"] == "spread" and pr["miss"] == "inside" and pr["density"] < 0.4 and nd >= 3:
+        # build keys sit one per slot of width `step`, misses inside the slots,
+        # so both stay within one slot width (<= 2 * span / (nd - 1)) of the build range
+        span = int(bk.max()) - int(bk.min())
+        slack = 2 * span // (nd - 1) + 1
+        assert int(pk.min()) >= int(bk.min()) - slack and int(pk.max()) <= int(bk.max()) + slack
+
+
+def test_selector_family2_covers_its_layouts():
+    seen = set()
+    for i in range(64):
+        pr = synth.selector_params(8, i, max_build_log2=26, min_build_log2=16, max_probe_log2=28, family=2)
+        seen.add((pr["layout"], pr["miss"]))
+        assert pr["n_probe"] <= 1 << 28 and (1 << 16) - 1 <= pr["n_build"] <= (1 << 26) + 1
+    assert seen == {("spread", "above"), ("spread", "inside"), ("full64", "inside")}
+
+
 @pytest.mark.gpu
 def test_generators_identical_on_gpu(gpu):
     for make in (lambda d: synth.plain_dense(seed=5, n_build=5000, n_probe=20000, device=d),
