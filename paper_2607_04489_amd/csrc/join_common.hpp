@@ -86,9 +86,9 @@ __device__ __forceinline__ void finish(EmitLds<NT, SCAP> &L, const EmitOut &o, u
 }
 
 // Registers of one probe sub-tile: up to IPT rows per thread, rows
-// lo + k * NT + threadIdx.x. Loading the next sub-tile before processing the
-// current one keeps global loads in flight across the LDS barriers (on gfx950
-// a barrier waits for LDS traffic only).
+// lo + k * NT + threadIdx.x. (Holding the next sub-tile in registers as well
+// was measured slower on gfx950: the extra registers cost more occupancy than
+// the overlap gained.)
 template <int IPT, typename K, typename PS>
 struct ProbeRegs {
   K key[IPT];
@@ -285,8 +285,8 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
   fill += total;
 }
 
-// Probe the rows [lo, hi) in sub-tiles of NT * IPT rows, prefetching each next
-// sub-tile while the current one is processed. Uniform across the workgroup.
+// Probe the rows [lo, hi) in sub-tiles of NT * IPT rows. Uniform across the
+// workgroup.
 template <int NT, int IPT, int SCAP, class Tab, typename K, typename PS>
 __device__ __forceinline__ void probe_range(const Tab &tab, const K *__restrict__ pk,
                                             const PS *__restrict__ pp,
@@ -295,13 +295,10 @@ __device__ __forceinline__ void probe_range(const Tab &tab, const K *__restrict_
                                             const EmitOut &o, uint64_t &cs) {
   constexpr uint64_t sub = uint64_t(NT) * IPT;
   if (lo >= hi) return;
-  ProbeRegs<IPT, K, PS> cur, nxt;
-  probe_load<NT, IPT>(cur, pk, pp, prow, lo, lo + sub < hi ? lo + sub : hi);
+  ProbeRegs<IPT, K, PS> cur;
   for (uint64_t t = lo; t < hi; t += sub) {
-    const uint64_t n0 = t + sub;
-    if (n0 < hi) probe_load<NT, IPT>(nxt, pk, pp, prow, n0, n0 + sub < hi ? n0 + sub : hi);
+    probe_load<NT, IPT>(cur, pk, pp, prow, t, t + sub < hi ? t + sub : hi);
     probe_process<NT, IPT, SCAP>(tab, cur, L, fill, o, cs);
-    cur = nxt;
   }
 }
 

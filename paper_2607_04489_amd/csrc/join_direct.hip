@@ -76,7 +76,7 @@ __global__ void k_direct_fill(const K *__restrict__ keys, const PB *__restrict__
 }
 
 // Each workgroup streams a contiguous range of probe rows (an equal share of
-// whole sub-tiles), so its prefetch of the next sub-tile is always useful.
+// whole sub-tiles).
 template <class Tab, typename K, typename PS>
 __global__ void __launch_bounds__(kNT) k_probe(Tab tab, const K *__restrict__ pk,
                                                const PS *__restrict__ pp, uint64_t n, EmitOut o) {

@@ -729,7 +729,7 @@ namespace eiger {
 namespace {
 
 constexpr int kCNT = 256;
-constexpr int kCIPT = 8;
+constexpr int kCIPT = 4;
 constexpr int kCSCAP = 4096;
 constexpr uint32_t kCTileMax = 16384;  // probe rows per work item (upper bound)
 constexpr int kXcds = 8;

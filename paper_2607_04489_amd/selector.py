@@ -32,7 +32,10 @@ DATA_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_d
 # inside the build range, full 64-bit key layouts
 DATA_PATH_WIDE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data",
                               "timings_mi355x_wide.jsonl")
-DATA_PATHS = (DATA_PATH, DATA_PATH_WIDE)
+# family 3: builds of 2^22..2^28 rows, probes up to 2^29 rows
+DATA_PATH_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data",
+                               "timings_mi355x_large.jsonl")
+DATA_PATHS = (DATA_PATH, DATA_PATH_WIDE, DATA_PATH_LARGE)
 FIXED_HASH_CLASS = 2  # GLOBAL_HASH at load factor 0.5
 
 

@@ -308,7 +308,10 @@ def selector_params(seed: int, idx: int, max_build_log2: float = 22.0, max_probe
     Family 2 widens what family 1 leaves out: probe rows = build rows * 2^U(0, 5);
     half of the instances put missing keys into the gaps between build keys (so
     the probe range equals the build range) instead of above it; and 40% of the
-    int64 instances spread their keys over the whole 64-bit range."""
+    int64 instances spread their keys over the whole 64-bit range.
+
+    Family 3 is family 2 with probe rows = build rows * 2^U(0, 6), meant for the
+    largest builds (the caller passes the size bounds)."""
     u = [_u01(seed, 200 + k, idx) for k in range(8)]
     n_build = int(round(2.0 ** (min_build_log2 + u[0] * (max_build_log2 - min_build_log2))))
     wide = u[1] < 0.5
@@ -316,7 +319,7 @@ def selector_params(seed: int, idx: int, max_build_log2: float = 22.0, max_probe
     dup = 1 if u[3] < 0.4 else 2 + int(u[3] * 1e6) % 15
     zipf_s = 1.5 * u[4]
     selectivity = 0.01 + 0.99 * u[5]
-    mult_log2 = 4.0 if family == 1 else 5.0
+    mult_log2 = {1: 4.0, 2: 5.0, 3: 6.0}[family]
     n_probe = int(min(round(n_build * 2.0 ** (mult_log2 * u[6])), 2 ** max_probe_log2))
     pr = {"n_build": n_build, "wide": wide, "density": density, "dup": dup, "zipf_s": zipf_s,
           "selectivity": selectivity, "n_probe": n_probe}
