@@ -458,8 +458,9 @@ __global__ void __launch_bounds__(kJNT)
     k_radix_join(const K *__restrict__ rk, const PB *__restrict__ rp, const uint32_t *__restrict__ rr,
                  const uint32_t *__restrict__ offR, const K *__restrict__ sk,
                  const PS *__restrict__ sp, const uint32_t *__restrict__ sr,
-                 const uint32_t *__restrict__ offS, const uint32_t *__restrict__ item_off, uint32_t F,
-                 uint32_t max_build, float lf, EmitOut o) {
+                 const uint32_t *__restrict__ offS, const uint32_t *__restrict__ item_off,
+                 const uint32_t *__restrict__ item_part, uint32_t F, uint32_t max_build, float lf,
+                 EmitOut o) {
   constexpr uint32_t MAXS = lds_max_slots<K, PB>();
   __shared__ K tk[MAXS];
   __shared__ uint32_t tr[MAXS];
@@ -469,13 +470,7 @@ __global__ void __launch_bounds__(kJNT)
   uint64_t cs = 0;
   const uint32_t nitems = item_off[F];
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
-    // partition p: item_off[p] <= it < item_off[p+1]
-    uint32_t lo = 0, hi = F;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (item_off[mid] <= it) lo = mid; else hi = mid;
-    }
-    const uint32_t p = lo;
+    const uint32_t p = item_part[it];
     const uint32_t tile = it - item_off[p];
     const uint32_t r0 = offR[p], r1 = offR[p + 1];
     const uint32_t s0 = offS[p] + tile * kJTile;
@@ -637,6 +632,15 @@ int partition_side(const K *keys, const P *pays, uint64_t n, SideBufs<K, P> &S, 
   return EIGER_OK;
 }
 
+// Partition of every work item: part[t] = p for off[p] <= t < off[p+1] (off is
+// the exclusive scan of the per-partition item counts), so a workgroup finds its
+// item's partition with one load.
+__global__ void k_item_part(const uint32_t *__restrict__ off, uint32_t F, uint32_t *__restrict__ part) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < F)
+    for (uint32_t t = off[p], e = off[p + 1]; t < e; ++t) part[t] = p;
+}
+
 uint64_t counters_len(uint64_t n, const PassPlan &pp) {
   uint64_t m = ub_chunks(n, 1) << pp.bits[0];
   if (pp.passes == 2) {
@@ -663,6 +667,8 @@ int radix_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   uint64_t *tmp = ws.take<uint64_t>(scan_tmp_elems(std::max<uint64_t>(nC, F + 1)));
   uint64_t *total = ws.take<uint64_t>(1);
   uint32_t *items = ws.take<uint32_t>(F + 1);
+  // each partition has at most ceil(its probe rows / kJTile) items
+  uint32_t *item_part = ws.take<uint32_t>(uint64_t(F) + (a.nS + kJTile - 1) / kJTile + 1);
   *ctr = c;
   if (!ws.base) return EIGER_OK;
   hipStream_t s = a.s;
@@ -680,10 +686,11 @@ int radix_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   EIGER_LAUNCH("radix_items", k_items, dim3((F + 1 + 255) / 256), dim3(256), 0, s, R.off, S.off, F,
                items);
   if ((rc = exclusive_scan_u32(items, items, F + 1, tmp, total, s))) return rc;
+  EIGER_LAUNCH("radix_items", k_item_part, dim3((F + 255) / 256), dim3(256), 0, s, items, F, item_part);
   EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
   const unsigned grid = static_cast<unsigned>(device_cu_count()) * 2;
   EIGER_LAUNCH("radix_join", (k_radix_join<K, PB, PS>), dim3(grid), dim3(kJNT), 0, s, fr.k, fr.p, fr.r,
-               R.off, fs.k, fs.p, fs.r, S.off, items, F, lim.max_build, lf, o);
+               R.off, fs.k, fs.p, fs.r, S.off, items, item_part, F, lim.max_build, lf, o);
   return EIGER_OK;
 }
 
@@ -826,8 +833,9 @@ template <typename K, typename PB, typename PS>
 __global__ void __launch_bounds__(kCNT)
     k_cache_probe(const Slot<K, PB> *__restrict__ table, const uint32_t *__restrict__ table_off,
                   const K *__restrict__ sk, const PS *__restrict__ sp, const uint32_t *__restrict__ sr,
-                  const uint32_t *__restrict__ offS, const uint32_t *__restrict__ tile_off, uint32_t F,
-                  uint32_t per_xcd, uint32_t ctile, int shared_mall, const uint32_t *dup, EmitOut o) {
+                  const uint32_t *__restrict__ offS, const uint32_t *__restrict__ tile_off,
+                  const uint32_t *__restrict__ tile_part, uint32_t F, uint32_t per_xcd, uint32_t ctile,
+                  int shared_mall, const uint32_t *dup, EmitOut o) {
   __shared__ EmitLds<kCNT, kCSCAP> L;
   uint64_t fill = 0;
   uint64_t cs = 0;
@@ -842,12 +850,7 @@ __global__ void __launch_bounds__(kCNT)
   const uint64_t xhi = shared_mall ? T : T * (x + 1) / kXcds;
   const uint64_t step = shared_mall ? gridDim.x : per_xcd;
   for (uint64_t t = xlo; t < xhi; t += step) {
-    uint32_t lo = 0, hi = F;  // tile_off[lo] <= t < tile_off[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (tile_off[mid] <= t) lo = mid; else hi = mid;
-    }
-    const uint32_t p = lo;
+    const uint32_t p = tile_part[t];
     const uint32_t s0 = offS[p] + static_cast<uint32_t>(t - tile_off[p]) * ctile;
     const uint32_t s1 = min(offS[p + 1], s0 + ctile);
     CacheTab<K, PB> tab{table + table_off[p], table_off[p + 1] - table_off[p], unique};
@@ -883,6 +886,8 @@ int radix_cache_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   uint64_t *total = ws.take<uint64_t>(1);
   uint32_t *table_off = ws.take<uint32_t>(F + 1);
   uint32_t *tile_off = ws.take<uint32_t>(F + 1);
+  // tiles hold at least 2048 probe rows, so a partition has at most ceil(rows / 2048)
+  uint32_t *tile_part = ws.take<uint32_t>(uint64_t(F) + (a.nS + 2047) / 2048 + 1);
   uint32_t *dup = ws.take<uint32_t>(1);
   Slot<K, PB> *table = ws.take<Slot<K, PB>>(tbound);
   *ctr = c;
@@ -921,6 +926,7 @@ int radix_cache_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
                lf, ctile, table_off, tile_off);
   if ((rc = exclusive_scan_u32(table_off, table_off, F + 1, tmp, total, s))) return rc;
   if ((rc = exclusive_scan_u32(tile_off, tile_off, F + 1, tmp, total, s))) return rc;
+  EIGER_LAUNCH("cache_sizes", k_item_part, dim3((F + 255) / 256), dim3(256), 0, s, tile_off, F, tile_part);
   if ((rc = fill_u32(reinterpret_cast<uint32_t *>(table), tbound * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
     return rc;
   EIGER_LAUNCH("cache_build", (k_cache_build<K, PB>), dim3(grid_for_rows(a.nR)), dim3(256), 0, s, bk,
@@ -930,7 +936,7 @@ int radix_cache_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
                bits, table_off, table, dup);
   EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
   EIGER_LAUNCH("cache_probe", (k_cache_probe<K, PB, PS>), dim3(per_xcd * kXcds), dim3(kCNT), 0, s, table,
-               table_off, fs.k, fs.p, fs.r, S.off, tile_off, F, per_xcd, ctile, shared_mall, dup, o);
+               table_off, fs.k, fs.p, fs.r, S.off, tile_off, tile_part, F, per_xcd, ctile, shared_mall, dup, o);
   return EIGER_OK;
 }
 
