@@ -24,7 +24,7 @@ namespace {
 
 constexpr uint32_t kBuildTile = 16384;
 constexpr int kBNT = 256;
-constexpr int kBIPT = 8;
+constexpr int kBIPT = 4;
 constexpr int kBSCAP = 4096;
 constexpr uint32_t kVarDirect = 0, kVarHash = 1;
 
