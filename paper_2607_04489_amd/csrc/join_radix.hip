@@ -453,6 +453,185 @@ __host__ __device__ constexpr uint32_t lds_max_slots() {
   return kTableBytes / (sizeof(K) + sizeof(PB) + sizeof(uint32_t));
 }
 
+// LDS table of one chunk of 32-bit build keys, grouped by key. Each distinct
+// key owns one 64-bit slot word  key << 32 | cursor << 16 | count  (count 0 =
+// empty; linear probing over distinct keys only); its build rows sit together
+// in rid[start, start + count) with start = cursor - count once placed, and the
+// key's payload sum (sign-extended, mod 2^64) is kept at psum[start]. A probe
+// stops at its key's slot, and its matches are one contiguous run.
+struct GrpTab {
+  static constexpr bool kHashed = false;
+  const unsigned long long *w;
+  const uint32_t *rid;
+  const uint64_t *psum;
+  uint32_t nslots;
+
+  __device__ __forceinline__ uint32_t home(int32_t key) const {
+    const uint32_t h = static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))));
+    return static_cast<uint32_t>((uint64_t(h) * nslots) >> 32);
+  }
+  __device__ __forceinline__ uint32_t next(uint32_t i) const { return (i + 1 == nslots) ? 0 : i + 1; }
+  __device__ __forceinline__ uint32_t find(int32_t key, uint32_t &start) const {
+    for (uint32_t i = home(key);; i = next(i)) {
+      const unsigned long long v = w[i];
+      const uint32_t c = static_cast<uint32_t>(v & 0xFFFFu);
+      if (c == 0) return 0;
+      if (static_cast<uint32_t>(v >> 32) == static_cast<uint32_t>(key)) {
+        start = static_cast<uint32_t>((v >> 16) & 0xFFFFu) - c;
+        return c;
+      }
+    }
+  }
+  __device__ __forceinline__ uint32_t lookup(int32_t key, uint32_t &first, uint64_t &ps) const {
+    uint32_t st = 0;
+    const uint32_t c = find(key, st);
+    if (c) {
+      first = rid[st];
+      ps += psum[st];
+    }
+    return c;
+  }
+  template <class F>
+  __device__ __forceinline__ void for_each(int32_t key, F f) const {
+    uint32_t st = 0;
+    const uint32_t c = find(key, st);
+    for (uint32_t j = 0; j < c; ++j) f(rid[st + j]);
+  }
+};
+
+// Build rows one grouped table holds at load factor lf: ns >= n / lf slots of
+// 8 bytes plus 12 bytes (row id, payload sum word) per row in kTableBytes.
+__host__ __device__ inline uint32_t grouped_max_build(float lf) {
+  return static_cast<uint32_t>(static_cast<float>(kTableBytes) / (8.0f / lf + 12.0f));
+}
+
+// Join one chunk [c0, c1) of a partition's 32-bit build rows with probe rows
+// [s0, s1) through a grouped table. Uniform across the workgroup.
+template <typename PB, typename PS>
+__device__ __forceinline__ void join_chunk_grouped(const int32_t *__restrict__ rk, const PB *__restrict__ rp,
+                                                   const uint32_t *__restrict__ rr, uint32_t c0, uint32_t c1,
+                                                   const int32_t *__restrict__ sk, const PS *__restrict__ sp,
+                                                   const uint32_t *__restrict__ sr, uint32_t s0, uint32_t s1,
+                                                   float lf, EmitLds<kJNT, kJSCAP> &L, uint64_t &fill,
+                                                   const EmitOut &o, uint64_t &cs) {
+  __shared__ __align__(16) unsigned char lds[kTableBytes];
+  const uint32_t nb = c1 - c0;
+  // slots: nb / lf + 1, at least 64, at most what fits beside the rows (> nb
+  // because nb <= grouped_max_build), so every walk reaches an empty slot
+  const uint32_t cap = (kTableBytes - nb * 12u) / 8u;
+  uint32_t ns = static_cast<uint32_t>(static_cast<float>(nb) / lf) + 1;
+  ns = ns < 64 ? 64 : ns;
+  ns = ns > cap ? cap : ns;
+  unsigned long long *W = reinterpret_cast<unsigned long long *>(lds);
+  uint64_t *ps = reinterpret_cast<uint64_t *>(lds + size_t(ns) * 8);
+  uint32_t *rid = reinterpret_cast<uint32_t *>(lds + size_t(ns) * 8 + size_t(nb) * 8);
+  GrpTab tab{W, rid, ps, ns};
+  for (uint32_t i = threadIdx.x; i < ns; i += kJNT) W[i] = 0;
+  __syncthreads();
+  // 1. one slot per distinct key, with its row count
+  for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
+    const uint32_t key = static_cast<uint32_t>(rk[j]);
+    uint32_t i = tab.home(rk[j]);
+    for (;;) {
+      unsigned long long v = W[i];
+      if ((v & 0xFFFFu) == 0) {
+        v = atomicCAS(&W[i], 0ull, (static_cast<unsigned long long>(key) << 32) | 1ull);
+        if (v == 0) break;  // claimed with count 1
+      }
+      if (static_cast<uint32_t>(v >> 32) == key) {
+        atomicAdd(&W[i], 1ull);
+        break;
+      }
+      i = tab.next(i);
+    }
+  }
+  __syncthreads();
+  // 2. group starts: exclusive scan of the counts in slot order (each thread a
+  //    contiguous run of slots), written into the cursor field
+  {
+    const uint32_t per = (ns + kJNT - 1) / kJNT;
+    const uint32_t lo = min(ns, threadIdx.x * per), hi = min(ns, lo + per);
+    uint32_t local = 0;
+    for (uint32_t i = lo; i < hi; ++i) local += static_cast<uint32_t>(W[i] & 0xFFFFu);
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan<kJNT>(local, L.scan, &tot);
+    for (uint32_t i = lo; i < hi; ++i) {
+      const unsigned long long v = W[i];
+      W[i] = (v & 0xFFFFFFFF0000FFFFull) | (static_cast<unsigned long long>(run) << 16);
+      run += static_cast<uint32_t>(v & 0xFFFFu);
+    }
+  }
+  __syncthreads();
+  // 3. place every row in its key's group (the cursor field advances to the end)
+  for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
+    const uint32_t key = static_cast<uint32_t>(rk[j]);
+    uint32_t i = tab.home(rk[j]);
+    while (static_cast<uint32_t>(W[i] >> 32) != key || (W[i] & 0xFFFFu) == 0) i = tab.next(i);
+    const uint32_t pos = static_cast<uint32_t>((atomicAdd(&W[i], 1ull << 16) >> 16) & 0xFFFFu);
+    rid[pos] = rr[j];
+    ps[pos] = static_cast<uint64_t>(sext(rp[j]));
+  }
+  __syncthreads();
+  // 4. payload sum of each group, kept at its start
+  for (uint32_t i = threadIdx.x; i < ns; i += kJNT) {
+    const unsigned long long v = W[i];
+    const uint32_t c = static_cast<uint32_t>(v & 0xFFFFu);
+    if (c) {
+      const uint32_t st = static_cast<uint32_t>((v >> 16) & 0xFFFFu) - c;
+      uint64_t sum = 0;
+      for (uint32_t q = 0; q < c; ++q) sum += ps[st + q];
+      ps[st] = sum;
+    }
+  }
+  __syncthreads();
+  probe_range<kJNT, kJIPT, kJSCAP>(tab, sk, sp, sr, s0, s1, L, fill, o, cs);
+}
+
+// Join one chunk of a partition through a multiset table (one slot per build
+// row; used for 64-bit keys). Uniform across the workgroup.
+template <typename K, typename PB, typename PS>
+__device__ __forceinline__ void join_chunk_multiset(const K *__restrict__ rk, const PB *__restrict__ rp,
+                                                    const uint32_t *__restrict__ rr, uint32_t c0, uint32_t c1,
+                                                    const K *__restrict__ sk, const PS *__restrict__ sp,
+                                                    const uint32_t *__restrict__ sr, uint32_t s0, uint32_t s1,
+                                                    float lf, EmitLds<kJNT, kJSCAP> &L, uint64_t &fill,
+                                                    const EmitOut &o, uint64_t &cs) {
+  constexpr uint32_t MAXS = lds_max_slots<K, PB>();
+  __shared__ K tk[MAXS];
+  __shared__ uint32_t tr[MAXS];
+  __shared__ PB tp[MAXS];
+  __shared__ uint32_t dup;
+  const uint32_t nb = c1 - c0;
+  uint32_t ns = static_cast<uint32_t>(static_cast<float>(nb) / lf) + 1;
+  ns = ns < 64 ? 64 : (ns > MAXS ? MAXS : ns);
+  for (uint32_t i = threadIdx.x; i < ns; i += kJNT) tr[i] = kEmpty;
+  if (threadIdx.x == 0) dup = 0;
+  __syncthreads();
+  LdsTab<K, PB> tab{tk, tr, tp, ns, false};
+  for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
+    const K key = rk[j];
+    uint32_t i = tab.home(key);
+    for (;;) {
+      if (atomicCAS(&tr[i], kEmpty, rr[j]) == kEmpty) {
+        tk[i] = key;
+        tp[i] = rp[j];
+        break;
+      }
+      i = (i + 1 == ns) ? 0 : i + 1;
+    }
+  }
+  __syncthreads();
+  // distinct build keys in this table let probes stop at their first match
+  for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
+    uint32_t cnt = 0;
+    tab.for_each(rk[j], [&](uint32_t) { ++cnt; });
+    if (cnt > 1) dup = 1;
+  }
+  __syncthreads();
+  tab.unique = dup == 0;
+  probe_range<kJNT, kJIPT, kJSCAP>(tab, sk, sp, sr, s0, s1, L, fill, o, cs);
+}
+
 template <typename K, typename PB, typename PS>
 __global__ void __launch_bounds__(kJNT)
     k_radix_join(const K *__restrict__ rk, const PB *__restrict__ rp, const uint32_t *__restrict__ rr,
@@ -461,10 +640,6 @@ __global__ void __launch_bounds__(kJNT)
                  const uint32_t *__restrict__ offS, const uint32_t *__restrict__ item_off,
                  const uint32_t *__restrict__ item_part, uint32_t F, uint32_t max_build, float lf,
                  EmitOut o) {
-  constexpr uint32_t MAXS = lds_max_slots<K, PB>();
-  __shared__ K tk[MAXS];
-  __shared__ uint32_t tr[MAXS];
-  __shared__ PB tp[MAXS];
   __shared__ EmitLds<kJNT, kJSCAP> L;
   uint64_t fill = 0;
   uint64_t cs = 0;
@@ -477,36 +652,10 @@ __global__ void __launch_bounds__(kJNT)
     const uint32_t s1 = min(offS[p + 1], s0 + kJTile);
     for (uint32_t c0 = r0; c0 < r1; c0 += max_build) {
       const uint32_t c1 = min(r1, c0 + max_build);
-      const uint32_t nb = c1 - c0;
-      uint32_t ns = static_cast<uint32_t>(static_cast<float>(nb) / lf) + 1;
-      ns = ns < 64 ? 64 : (ns > MAXS ? MAXS : ns);
-      for (uint32_t i = threadIdx.x; i < ns; i += kJNT) tr[i] = kEmpty;
-      __syncthreads();
-      __shared__ uint32_t dup;
-      if (threadIdx.x == 0) dup = 0;
-      LdsTab<K, PB> tab{tk, tr, tp, ns, false};
-      for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
-        const K key = rk[j];
-        uint32_t i = tab.home(key);
-        for (;;) {
-          if (atomicCAS(&tr[i], kEmpty, rr[j]) == kEmpty) {
-            tk[i] = key;
-            tp[i] = rp[j];
-            break;
-          }
-          i = (i + 1 == ns) ? 0 : i + 1;
-        }
-      }
-      __syncthreads();
-      // distinct build keys in this table let probes stop at their first match
-      for (uint32_t j = c0 + threadIdx.x; j < c1; j += kJNT) {
-        uint32_t cnt = 0;
-        tab.for_each(rk[j], [&](uint32_t) { ++cnt; });
-        if (cnt > 1) dup = 1;
-      }
-      __syncthreads();
-      tab.unique = dup == 0;
-      probe_range<kJNT, kJIPT, kJSCAP>(tab, sk, sp, sr, s0, s1, L, fill, o, cs);
+      if constexpr (sizeof(K) == 4)
+        join_chunk_grouped<PB, PS>(rk, rp, rr, c0, c1, sk, sp, sr, s0, s1, lf, L, fill, o, cs);
+      else
+        join_chunk_multiset<K, PB, PS>(rk, rp, rr, c0, c1, sk, sp, sr, s0, s1, lf, L, fill, o, cs);
       __syncthreads();
     }
   }
@@ -699,6 +848,11 @@ int radix_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
 RadixLimits radix_limits(int32_t kdt, int32_t bpdt, float lf) {
   if (!(lf > 0.f) || lf > 0.9f) lf = 0.5f;
   RadixLimits r{};
+  if (kdt == EIGER_INT32) {  // grouped tables (join_chunk_grouped)
+    r.max_build = grouped_max_build(lf);
+    r.max_slots = static_cast<uint32_t>(kTableBytes / 8);
+    return r;
+  }
   const uint32_t slot = static_cast<uint32_t>(dtype_size(kdt) + dtype_size(bpdt) + 4);
   r.max_slots = kTableBytes / slot;
   r.max_build = static_cast<uint32_t>(static_cast<float>(r.max_slots) * lf);
