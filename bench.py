@@ -348,21 +348,26 @@ def main():
         return pl, eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, pl,
                            workspace=ws_join, outputs=outs)
 
-    log(f"plan {plan.describe()}; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        pl, res = step(sel, forced)
-    torch.cuda.synchronize()
+    def timed(selector, forced_plan, warmup):
+        """Mean ms per step over args.steps steps, with the library's per-kernel
+        HIP-event timing on (for every plan alike, so comparisons carry the
+        same overhead), plus the per-kernel table and the last result."""
+        for _ in range(warmup):
+            step(selector, forced_plan)
+        torch.cuda.synchronize()
+        eg.profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            last = step(selector, forced_plan)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        table = eg.profile_read()
+        eg.profile_enable(False)
+        return dt / args.steps * 1e3, table, last
 
-    eg.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        pl, res = step(sel, forced)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = eg.profile_read()
-    eg.profile_enable(False)
-    ms = dt / args.steps * 1e3
+    log(f"plan {plan.describe()}; warmup {args.warmup}")
+    ms, prof, (pl, res) = timed(sel, forced, args.warmup)
     log(f"timed {args.steps} steps: {ms:.3f} ms/step, count={res.count}")
 
     # sanity against the generator's record (no oracle in the timed path)
@@ -393,14 +398,7 @@ def main():
     if not args.no_compare and sel != eg.SEL_FIXED_HASH:
         fplan = eg.join_plan(sb, sp, eg.SEL_FIXED_HASH)
         ws_join, outs = prepare(fplan)
-        for _ in range(max(1, args.warmup)):
-            step(eg.SEL_FIXED_HASH, None)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            _, r2 = step(eg.SEL_FIXED_HASH, None)
-        torch.cuda.synchronize()
-        fms = (time.perf_counter() - t1) / args.steps * 1e3
+        fms, _, (_, r2) = timed(eg.SEL_FIXED_HASH, None, max(1, args.warmup))
         assert (r2.count, r2.checksum) == (res.count, res.checksum)
         compare = {"fixed_hash_ms_per_step": round(fms, 4), "speedup_vs_fixed_hash": round(fms / ms, 3),
                    "plan": fplan.describe()}
@@ -410,13 +408,7 @@ def main():
     if not args.no_learned and not args.force and sel == eg.SEL_LEARNED:
         rplan = eg.join_plan(sb, sp, eg.SEL_RULE)
         ws_join, outs = prepare(rplan)
-        step(eg.SEL_RULE, None)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            _, r3 = step(eg.SEL_RULE, None)
-        torch.cuda.synchronize()
-        rms = (time.perf_counter() - t1) / args.steps * 1e3
+        rms, _, (_, r3) = timed(eg.SEL_RULE, None, max(1, args.warmup))
         assert (r3.count, r3.checksum) == (res.count, res.checksum)
         rule_cmp = {"plan": rplan.describe(), "ms_per_step": round(rms, 4), "learned_speedup": round(rms / ms, 3)}
         log(f"rule planner: {rplan.describe()} {rms:.3f} ms/step")

@@ -16,6 +16,10 @@ SPECS = [
     ("radix_b9", eg.RADIX, 9, 1, 0.75),
     ("radix_b10p2", eg.RADIX, 10, 2, 0.5),
     ("radix_b15p2", eg.RADIX, 15, 2, 0.6),
+    # load factor 0.9: the LDS table's largest row capacity (grouped tables for
+    # 32-bit keys fill their LDS almost exactly) and, at 4 bits, partitions
+    # larger than one table, so several chunks per partition
+    ("radix_b4_lf90", eg.RADIX, 4, 1, 0.9),
     ("cache_b1", eg.RADIX_CACHE, 1, 1, 0.5),
     ("cache_b6", eg.RADIX_CACHE, 6, 1, 0.75),
     ("cache_b10", eg.RADIX_CACHE, 10, 1, 0.5),
