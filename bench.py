@@ -54,15 +54,17 @@ def sources_digest(name):
     return h.hexdigest()[:16]
 
 
-def traffic_for(name, workload):
+def traffic_for(name, workload, plan):
     """HBM bytes per launch of `name` from the committed rocprofv3 counter
-    record, or None when there is none or the kernel's sources changed since."""
+    record, or None when there is none, or it was taken on another workload or
+    plan, or the kernel's sources changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f).get(name)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("workload") != workload or rec.get("sources_sha") != sources_digest(name):
+    if (not rec or rec.get("workload") != workload or rec.get("plan") != plan
+            or rec.get("sources_sha") != sources_digest(name)):
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -441,7 +443,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": (lambda t: round(t / 1e9, 3) if t else None)(traffic_for(dom, args.workload)),
+                     "traffic": (lambda t: round(t / 1e9, 3) if t else None)(traffic_for(dom, args.workload, pl.describe())),
                      "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "alg_bytes_per_launch": int(dom_bytes / max(dom_launches, 1)) if dom_bytes else None,
                      "avg_launch_ms": round(dom_ms / max(dom_launches, 1), 5)},
