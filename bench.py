@@ -288,8 +288,9 @@ def main():
         print(json.dumps(bench_batched(autotune=args.autotune)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(statistics would merge by all-reduce and the probe side would shard by row "
+              "range); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -261,8 +261,13 @@ int eiger_join_batch_destroy(void *handle);
 /* Number of fp32 parameters of the selector MLP (6288). */
 int64_t eiger_mlp_param_count(void);
 
-/* Features of a (build, probe) pair of statistics, un-normalized (HOST out[16]).
- * The list is in the design doc; all are finite for any valid statistics. */
+/* Features of a (build, probe) pair of statistics, un-normalized (HOST out[16]),
+ * in this order (R = build, S = probe, d = distinct estimate, r = max - min + 1):
+ * log2(1+|R|), log2(1+|S|), log2(1+d_R), log2(1+d_S), log2(1+r_R), log2(1+r_S),
+ * 1 for int64 keys else 0, min(1, d_R/|R|), min(1, d_S/|S|), log2(|R|/d_R) (>= 0),
+ * log2(d_R/r_R) clamped to [-64, 0], overlap of the key ranges as a share of r_S,
+ * log2(|S|/|R|), log2(1 + |R||S|/max(d_R, d_S) * overlap), log2(1 + |S|/d_R),
+ * log2(1 + d_S/d_R). All are finite for any valid statistics. */
 int eiger_selector_features(const eiger_stats_t *build, const eiger_stats_t *probe, float *out);
 
 /* The plan of class `cls` (0..EIGER_SEL_CLASSES-1) for these statistics.

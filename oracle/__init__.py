@@ -29,7 +29,7 @@ _LIB = os.path.join(_HERE, "_liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
-HLL_P = 14  # 2^14 registers; the paper does not fix the precision (reading in the design doc)
+HLL_P = 14  # 2^14 registers; the paper does not fix the precision, this is the library's choice
 
 
 def build(force: bool = False) -> str:

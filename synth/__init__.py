@@ -15,7 +15,9 @@ is also how unique keys are made without a uniqueness check.
 
 The workload shapes follow the paper's join microbenchmarks (Section 5.2:
 a smaller build side R, a larger probe side S, a match ratio = share of S
-rows with a partner in R) and the star-schema stand-ins listed in the design doc.
+rows with a partner in R), and stand in for star-schema joins: a
+dimension-like build side with unique or duplicated keys and a fact-like
+probe side whose keys follow a uniform, sampled or Zipf distribution.
 """
 from __future__ import annotations
 
