@@ -69,7 +69,7 @@ def traffic_for(name, workload, plan):
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
-def summarize_profile(d, workload, kernel):
+def summarize_profile(d, workload, kernel, plan=None):
     """Read rocprofv3 CSV output under directory d (p_trace, p_fetch, p_write,
     p_cfetch, p_cwrite from the commands in the profile summary) and print the
     traffic record of `kernel` (largest launches) plus a kernel-time table."""
@@ -105,7 +105,7 @@ def summarize_profile(d, workload, kernel):
         short = n.split("::")[-1].split("(")[0] if "::" in n else n
         table.append((float(r["TotalDurationNs"]), short[:60], int(r["Calls"]), float(r["AverageNs"])))
     table.sort(reverse=True)
-    rec = {"workload": workload, "kernel": kernel, "sources_sha": sources_digest(kernel),
+    rec = {"workload": workload, "kernel": kernel, "plan": plan, "sources_sha": sources_digest(kernel),
            "fetch_bytes_per_launch": int(fetch), "write_bytes_per_launch": int(write),
            "fetch_scale": round(fs, 4), "write_scale": round(ws_, 4)}
     print(json.dumps(rec))
@@ -276,12 +276,15 @@ def main():
     ap.add_argument("--summarize-profile", default="", metavar="DIR",
                     help="summarize rocprofv3 CSV output under DIR for --kernel and exit (no GPU)")
     ap.add_argument("--kernel", default="hash_probe")
+    ap.add_argument("--plan", default=None,
+                    help="with --summarize-profile: the profiled run's plan as JSON (its 'plan {...}' log line)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-joins comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the rule-planner comparison of the learned plan")
     ap.add_argument("--autotune", action="store_true", help="autotune the batched graph before timing it")
     args = ap.parse_args()
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.workload, args.kernel)
+        summarize_profile(args.summarize_profile, args.workload, args.kernel,
+                          json.loads(args.plan.replace("'", '"')) if args.plan else None)
         return
     if args.workload == "batched":
         import torch  # noqa: F401
