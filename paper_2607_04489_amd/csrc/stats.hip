@@ -119,17 +119,38 @@ __device__ __forceinline__ uint32_t bytewise_max(uint32_t a, uint32_t b) {
   return r;
 }
 
-// Byte-wise max of the per-workgroup registers; block 0 also reduces min/max.
-__global__ void __launch_bounds__(256) k_stats_final(const uint32_t *__restrict__ part_regs, int groups,
+// Registers are merged by byte-wise max. Above 2 * kSlices workgroups this
+// takes two stages, so that many loads are in flight: stage 1 reduces slice y
+// of the per-workgroup register arrays (groups g = y, y + kSlices, ...) for 256
+// words per block; stage 2 merges the slices and, in block 0, the
+// per-workgroup min/max. (One thread per word over all workgroups took ~0.12 ms
+// for 512 workgroups; two stages take ~0.016 ms.)
+constexpr int kSlices = 16;
+
+__global__ void __launch_bounds__(256) k_stats_merge(const uint32_t *__restrict__ part_regs, int groups,
+                                                     uint32_t *__restrict__ slice_regs) {
+  const int word = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  uint32_t r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int g = y;
+  for (; g + 7 * kSlices < groups; g += 8 * kSlices) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = bytewise_max(r[u], part_regs[uint64_t(g + u * kSlices) * kWords + word]);
+  }
+  for (; g < groups; g += kSlices) r[0] = bytewise_max(r[0], part_regs[uint64_t(g) * kWords + word]);
+#pragma unroll
+  for (int u = 1; u < 8; ++u) r[0] = bytewise_max(r[0], r[u]);
+  slice_regs[uint64_t(y) * kWords + word] = r[0];
+}
+
+__global__ void __launch_bounds__(256) k_stats_final(const uint32_t *__restrict__ slice_regs, int slices,
                                                      uint32_t *__restrict__ regs_out,
-                                                     const int64_t *__restrict__ part_mm,
+                                                     const int64_t *__restrict__ part_mm, int groups,
                                                      int64_t *__restrict__ mm_out) {
   const int word = blockIdx.x * 256 + threadIdx.x;
-  if (word < kWords) {
-    uint32_t r = 0;
-    for (int g = 0; g < groups; ++g) r = bytewise_max(r, part_regs[uint64_t(g) * kWords + word]);
-    regs_out[word] = r;
-  }
+  uint32_t r = 0;
+  for (int y = 0; y < slices; ++y) r = bytewise_max(r, slice_regs[uint64_t(y) * kWords + word]);
+  regs_out[word] = r;
   if (blockIdx.x == 0) {
     __shared__ int64_t red[2][4];
     int64_t mn = INT64_MAX, mx = INT64_MIN;
@@ -166,6 +187,7 @@ int stats_groups(int64_t n, int32_t dtype) {
 
 struct StatsLayout {
   uint32_t *part_regs;
+  uint32_t *slice_regs;
   int64_t *part_mm;
   uint32_t *regs;
   int64_t *mm;
@@ -174,6 +196,7 @@ struct StatsLayout {
 StatsLayout stats_layout(Workspace &ws, int groups) {
   StatsLayout L;
   L.part_regs = ws.take<uint32_t>(size_t(groups) * kWords);
+  L.slice_regs = ws.take<uint32_t>(size_t(kSlices) * kWords);
   L.part_mm = ws.take<int64_t>(size_t(groups) * 2);
   L.regs = ws.take<uint32_t>(kWords);
   L.mm = ws.take<int64_t>(2);
@@ -265,8 +288,15 @@ extern "C" int eiger_stats(eiger_column keys, eiger_stats_t *out, uint8_t *hll_r
     EIGER_LAUNCH("stats_partial", k_stats_partial<int64_t>, dim3(groups), dim3(kStatsThreads), 0, s,
                  static_cast<const int64_t *>(keys.data), uint64_t(keys.n), L.part_regs, L.part_mm);
   }
-  EIGER_LAUNCH("stats_final", k_stats_final, dim3(kWords / 256), dim3(256), 0, s, L.part_regs, groups,
-               L.regs, L.part_mm, L.mm);
+  if (groups <= 2 * kSlices) {  // few workgroups: one merge launch over them all
+    EIGER_LAUNCH("stats_final", k_stats_final, dim3(kWords / 256), dim3(256), 0, s, L.part_regs, groups, L.regs,
+                 L.part_mm, groups, L.mm);
+  } else {
+    EIGER_LAUNCH("stats_final", k_stats_merge, dim3(kWords / 256, kSlices), dim3(256), 0, s, L.part_regs,
+                 groups, L.slice_regs);
+    EIGER_LAUNCH("stats_final", k_stats_final, dim3(kWords / 256), dim3(256), 0, s, L.slice_regs, kSlices,
+                 L.regs, L.part_mm, groups, L.mm);
+  }
   std::vector<uint8_t> regs(kHllM);
   int64_t mm[2];
   EIGER_HIP(hipMemcpyAsync(regs.data(), L.regs, kHllM, hipMemcpyDeviceToHost, s));

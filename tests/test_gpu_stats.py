@@ -21,7 +21,9 @@ def check(col):
     return st
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 4099, 65536, 1000003])
+# 1048576 / 1081344 int32 rows: 32 / 33 partial sketches, the two sides of the
+# switch to the two-stage register merge (int64: 64 / 66)
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 4099, 65536, 1000003, 1048576, 1081344])
 @pytest.mark.parametrize("dtype", [torch.int32, torch.int64])
 def test_stats_sizes(gpu, n, dtype):
     lo, hi = (-(1 << 31), (1 << 31) - 1) if dtype == torch.int32 else (-(1 << 63), (1 << 63) - 1)
