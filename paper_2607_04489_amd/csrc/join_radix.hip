@@ -224,13 +224,15 @@ __global__ void __launch_bounds__(kPNT)
                       const uint32_t *__restrict__ C, K *__restrict__ okeys, P *__restrict__ opays,
                       uint32_t *__restrict__ orows) {
   constexpr int G = kWcGroup;
+  static_assert(MAXB <= 256, "bucket ids of tile positions are kept in one byte");
   __shared__ K lk[kPTile];
   __shared__ P lp[kPTile];
   __shared__ uint32_t lr[kPTile];
+  __shared__ uint8_t lb[kPTile];
   __shared__ K qk[MAXB * G];
   __shared__ P qp[MAXB * G];
   __shared__ uint32_t qr[MAXB * G];
-  __shared__ uint32_t hist[MAXB], loff[MAXB], gcur[MAXB], pend[MAXB], emit[MAXB], eoff[MAXB + 1];
+  __shared__ uint32_t hist[MAXB], loff[MAXB], gcur[MAXB], pend[MAXB], emit[MAXB];
   const uint32_t c = blockIdx.x;
   if (c >= cpre[nseg]) return;
   const uint32_t B = 1u << bits;
@@ -261,38 +263,29 @@ __global__ void __launch_bounds__(kPNT)
     }
     if (t0 + kPTile < hi) load_part_tile<K, P, kRows>(nkey, npay, nrow, keys, pays, rows, t0 + kPTile, hi);
     __syncthreads();
-    // wave 0: exclusive scans of the tile histogram (-> loff) and of the
-    // tuples each bucket emits this tile (-> eoff); lane l owns MAXB/64 buckets
+    // wave 0: exclusive scan of the tile histogram (-> loff) and, per bucket,
+    // how many tuples leave this tile: pending ones first, then the head of the
+    // tile run, up to the last kWcGroup-aligned output index (-> emit)
     if (threadIdx.x < 64) {
       constexpr int PER = MAXB / 64;
-      uint32_t h[PER], e[PER], hs = 0, es = 0;
+      uint32_t h[PER], hs = 0;
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const uint32_t b = threadIdx.x * PER + j;
         h[j] = b < B ? hist[b] : 0u;
-        e[j] = 0;
-        if (b < B) {
-          const uint32_t end = (gcur[b] + pend[b] + h[j]) & ~uint32_t(G - 1);
-          e[j] = end > gcur[b] ? end - gcur[b] : 0u;
-        }
         hs += h[j];
-        es += e[j];
       }
-      const uint32_t hx = wave_inclusive_scan(hs) - hs;
-      const uint32_t ex = wave_inclusive_scan(es) - es;
-      uint32_t hr = hx, er = ex;
+      uint32_t hr = wave_inclusive_scan(hs) - hs;
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const uint32_t b = threadIdx.x * PER + j;
         if (b < B) {
+          const uint32_t end = (gcur[b] + pend[b] + h[j]) & ~uint32_t(G - 1);
           loff[b] = hr;
-          eoff[b] = er;
-          emit[b] = e[j];
+          emit[b] = end > gcur[b] ? end - gcur[b] : 0u;
         }
         hr += h[j];
-        er += e[j];
       }
-      if (threadIdx.x == 63) eoff[B] = er;
     }
     __syncthreads();
 #pragma unroll
@@ -303,51 +296,45 @@ __global__ void __launch_bounds__(kPNT)
         lk[pos] = key[k];
         lp[pos] = pay[k];
         lr[pos] = row[k];
+        lb[pos] = static_cast<uint8_t>(bk[k]);
       }
     }
     __syncthreads();
-    // emit whole groups: pending tuples first, then the head of the tile run
-    const uint32_t etot = eoff[B];
-    for (uint32_t e = threadIdx.x; e < etot; e += kPNT) {
-      uint32_t l = 0, r = B;  // eoff[l] <= e < eoff[r]
-      while (r - l > 1) {
-        const uint32_t m = (l + r) / 2;
-        if (eoff[m] <= e) l = m; else r = m;
+    // Out: tuple j of bucket b's emitted run (pending tuples are j < pend[b],
+    // tile position p is j = pend[b] + p - loff[b]) goes to gcur[b] + j.
+    const uint32_t n = t1 - t0;
+    for (uint32_t q = threadIdx.x; q < B * G; q += kPNT) {
+      const uint32_t b = q / G, j = q % G;
+      if (j < pend[b] && emit[b]) {
+        okeys[gcur[b] + j] = qk[q];
+        opays[gcur[b] + j] = qp[q];
+        orows[gcur[b] + j] = qr[q];
       }
-      const uint32_t b = l, k = e - eoff[b], pb = pend[b];
-      const uint32_t dst = gcur[b] + k;
-      if (k < pb) {
-        okeys[dst] = qk[b * G + k];
-        opays[dst] = qp[b * G + k];
-        orows[dst] = qr[b * G + k];
-      } else {
-        const uint32_t src = loff[b] + (k - pb);
-        okeys[dst] = lk[src];
-        opays[dst] = lp[src];
-        orows[dst] = lr[src];
+    }
+    for (uint32_t p = threadIdx.x; p < n; p += kPNT) {
+      const uint32_t b = lb[p], j = pend[b] + p - loff[b];
+      if (j < emit[b]) {
+        okeys[gcur[b] + j] = lk[p];
+        opays[gcur[b] + j] = lp[p];
+        orows[gcur[b] + j] = lr[p];
       }
     }
     __syncthreads();
-    // keep the remainder (fewer than G tuples) for the next tile
+    // Kept: the rest of each bucket's run (fewer than kWcGroup tuples) moves to
+    // the front of its pending buffer, in order.
+    for (uint32_t p = threadIdx.x; p < n; p += kPNT) {
+      const uint32_t b = lb[p], j = pend[b] + p - loff[b];
+      if (j >= emit[b]) {
+        const uint32_t q = b * G + (j - emit[b]);
+        qk[q] = lk[p];
+        qp[q] = lp[p];
+        qr[q] = lr[p];
+      }
+    }
+    __syncthreads();
     for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
-      const uint32_t pb = pend[b], h = hist[b], e = emit[b];
-      if (e == 0) {
-        for (uint32_t i = 0; i < h; ++i) {
-          qk[b * G + pb + i] = lk[loff[b] + i];
-          qp[b * G + pb + i] = lp[loff[b] + i];
-          qr[b * G + pb + i] = lr[loff[b] + i];
-        }
-        pend[b] = pb + h;
-      } else {
-        const uint32_t keep = pb + h - e;  // < G; all pending tuples were emitted
-        for (uint32_t i = 0; i < keep; ++i) {
-          qk[b * G + i] = lk[loff[b] + h - keep + i];
-          qp[b * G + i] = lp[loff[b] + h - keep + i];
-          qr[b * G + i] = lr[loff[b] + h - keep + i];
-        }
-        pend[b] = keep;
-        gcur[b] += e;
-      }
+      pend[b] = pend[b] + hist[b] - emit[b];
+      gcur[b] += emit[b];
       hist[b] = 0;
     }
 #pragma unroll
@@ -359,12 +346,12 @@ __global__ void __launch_bounds__(kPNT)
     __syncthreads();
   }
   // chunk end: the remaining tuples of every bucket
-  for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
-    for (uint32_t i = 0; i < pend[b]; ++i) {
-      const uint32_t dst = gcur[b] + i;
-      okeys[dst] = qk[b * G + i];
-      opays[dst] = qp[b * G + i];
-      orows[dst] = qr[b * G + i];
+  for (uint32_t q = threadIdx.x; q < B * G; q += kPNT) {
+    const uint32_t b = q / G, j = q % G;
+    if (j < pend[b]) {
+      okeys[gcur[b] + j] = qk[q];
+      opays[gcur[b] + j] = qp[q];
+      orows[gcur[b] + j] = qr[q];
     }
   }
 }
