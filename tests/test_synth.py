@@ -108,6 +108,17 @@ def test_selector_family2_covers_its_layouts():
     assert seen == {("spread", "above"), ("spread", "inside"), ("full64", "inside")}
 
 
+def test_selector_family3_sizes():
+    """Family 3: builds 2^22..2^28 rows, probe/build ratio up to 2^6, probes capped at 2^29."""
+    ratios = []
+    for i in range(64):
+        pr = synth.selector_params(9, i, max_build_log2=28, min_build_log2=22, max_probe_log2=29, family=3)
+        assert (1 << 22) - 1 <= pr["n_build"] <= (1 << 28) + 1 and pr["n_probe"] <= 1 << 29
+        assert pr["family"] == 3 and pr["layout"] in ("spread", "full64")
+        ratios.append(pr["n_probe"] / pr["n_build"])
+    assert max(ratios) > 16 and min(ratios) >= 1
+
+
 @pytest.mark.gpu
 def test_generators_identical_on_gpu(gpu):
     for make in (lambda d: synth.plain_dense(seed=5, n_build=5000, n_probe=20000, device=d),
