@@ -87,8 +87,21 @@ __global__ void __launch_bounds__(kPNT)
   const uint32_t lc = c - cpre[s], nch = cpre[s + 1] - cpre[s];
   const uint32_t lo = seg_off[s] + lc * kChunk;
   const uint32_t hi = min(seg_off[s + 1], lo + kChunk);
-  for (uint32_t i = lo + threadIdx.x; i < hi; i += kPNT)
-    atomicAdd(&hist[bucket_of(static_cast<uint64_t>(sext(keys[i])), shift, B - 1)], 1u);
+  // 8 keys per thread are loaded before any is counted, so the loads overlap
+  constexpr int U = 8;
+  for (uint32_t i0 = lo; i0 < hi; i0 += kPNT * U) {
+    K kk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = i0 + u * kPNT + threadIdx.x;
+      if (i < hi) kk[u] = keys[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = i0 + u * kPNT + threadIdx.x;
+      if (i < hi) atomicAdd(&hist[bucket_of(static_cast<uint64_t>(sext(kk[u])), shift, B - 1)], 1u);
+    }
+  }
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < B; b += kPNT) C[uint64_t(cpre[s]) * B + uint64_t(b) * nch + lc] = hist[b];
 }
