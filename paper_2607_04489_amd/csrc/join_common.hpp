@@ -223,31 +223,31 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     fill = 0;
   }
   if (total > SCAP) {
-    // More matches than the stage holds (duplicated build keys): stage the
-    // tile one row slot k at a time (NT rows per round), so these pairs are
-    // also written contiguously; only a round that alone overflows the stage
-    // writes straight to its reserved range.
+    // More matches than the stage holds (duplicated build keys; the stage is
+    // empty here): reserve the sub-tile's whole output range with one atomic,
+    // then stage it one row slot k at a time (NT rows per round) and copy each
+    // round to its place in the range, so these pairs are also written
+    // contiguously; a round that alone overflows the stage writes straight
+    // into the range.
+    const uint64_t base = reserve(L, o, total);
+    uint64_t done = 0;  // pairs of this sub-tile placed so far (uniform)
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       uint32_t tk;
       const uint32_t ok = block_exclusive_scan<NT>(cnt[k], L.scan, &tk);
       if (tk == 0) continue;
-      if (fill + tk > SCAP) {
-        flush(L, o, static_cast<uint32_t>(fill));
-        fill = 0;
-      }
       if (tk > SCAP) {
-        const uint64_t base = reserve(L, o, tk);
-        uint64_t pos = base + ok;
+        uint64_t pos = base + done + ok;
         if (cnt[k] == 1) {
           put_pair(o, pos, first[k], r.rid[k]);
         } else if (cnt[k] > 1) {
           const uint32_t rr = r.rid[k];
           tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
         }
+        done += tk;
         continue;
       }
-      uint32_t pos = static_cast<uint32_t>(fill) + ok;
+      uint32_t pos = ok;
       if (cnt[k] == 1) {
         L.b[pos] = first[k];
         L.p[pos] = r.rid[k];
@@ -260,7 +260,9 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
         });
       }
       __syncthreads();
-      fill += tk;
+      for (uint32_t i = threadIdx.x; i < tk; i += NT) put_pair(o, base + done + i, L.b[i], L.p[i]);
+      __syncthreads();
+      done += tk;
     }
     (void)off;
     return;
