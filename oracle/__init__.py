@@ -33,10 +33,11 @@ HLL_P = 14  # 2^14 registers; the paper does not fix the precision, this is the 
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (plain -O2, OpenMP for the totals loop)."""
+    """Compile the C oracle with gcc (-O3, OpenMP for the sorts and the totals
+    loop; no -march=native: the library may run on another host's CPU)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                                "-Wall", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -50,11 +51,11 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             i64, pi64, pu64 = ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p
             vp = ctypes.c_void_p
-            lib.oracle_join_sortmerge.argtypes = [i64, vp, vp, i64, vp, vp, vp, i64, pi64, pi64]
+            lib.oracle_join_sortmerge.argtypes = [i64, vp, vp, i64, vp, vp, vp, i64, ctypes.c_int, pi64, pi64]
             lib.oracle_join_sortmerge.restype = ctypes.c_int
             lib.oracle_join_totals.argtypes = [i64, vp, vp, i64, vp, vp, ctypes.c_int, pi64, pi64]
             lib.oracle_join_totals.restype = ctypes.c_int
-            lib.oracle_probe_matches.argtypes = [i64, vp, vp, i64, vp, vp, vp, i64]
+            lib.oracle_probe_matches.argtypes = [i64, vp, vp, i64, vp, vp, vp, i64, ctypes.c_int]
             lib.oracle_probe_matches.restype = ctypes.c_int
             lib.oracle_fmix64.argtypes = [ctypes.c_uint64]
             lib.oracle_fmix64.restype = ctypes.c_uint64
@@ -79,24 +80,24 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def join_sortmerge(kR, pR, kS, pS, with_pairs: bool = True):
+def join_sortmerge(kR, pR, kS, pS, with_pairs: bool = True, threads: int = 1):
     """Inner equi-join by sort-merge (Section 3.2, Table 1; result definition in
     the module docstring of eiger_oracle.c). Returns (pairs, count, checksum);
     pairs is the canonical ascending u64 array of (build_row << 32 | probe_row),
-    or None when with_pairs is False."""
+    or None when with_pairs is False. `threads` only speeds up the sorts."""
     lib = _load()
     kR, pR, kS, pS = map(_as_i64, (kR, pR, kS, pS))
     assert kR.shape == pR.shape and kS.shape == pS.shape
     cnt, cs = ctypes.c_int64(), ctypes.c_int64()
     rc = lib.oracle_join_sortmerge(len(kR), _ptr(kR), _ptr(pR), len(kS), _ptr(kS), _ptr(pS),
-                                   None, 0, ctypes.byref(cnt), ctypes.byref(cs))
+                                   None, 0, int(threads), ctypes.byref(cnt), ctypes.byref(cs))
     if rc < 0:
         raise MemoryError("oracle_join_sortmerge")
     if not with_pairs:
         return None, cnt.value, cs.value
     pairs = np.empty(max(cnt.value, 1), dtype=np.uint64)
     rc = lib.oracle_join_sortmerge(len(kR), _ptr(kR), _ptr(pR), len(kS), _ptr(kS), _ptr(pS),
-                                   _ptr(pairs), cnt.value, ctypes.byref(cnt), ctypes.byref(cs))
+                                   _ptr(pairs), cnt.value, int(threads), ctypes.byref(cnt), ctypes.byref(cs))
     if rc != 0:
         raise RuntimeError(f"oracle_join_sortmerge rc={rc}")
     return pairs[: cnt.value], cnt.value, cs.value
@@ -115,7 +116,7 @@ def join_totals(kR, pR, kS, pS, threads: int = 1):
     return cnt.value, cs.value
 
 
-def probe_matches(kR, kS, rows):
+def probe_matches(kR, kS, rows, threads: int = 1):
     """For each queried probe row, the ascending build row ids with the same key.
     Returns (offsets[len(rows)+1], ids)."""
     lib = _load()
@@ -123,12 +124,13 @@ def probe_matches(kR, kS, rows):
     q = _as_i64(rows)
     assert q.size == 0 or (q.min() >= 0 and q.max() < len(kS))
     offs = np.zeros(len(q) + 1, dtype=np.int64)
-    rc = lib.oracle_probe_matches(len(kR), _ptr(kR), _ptr(kS), len(q), _ptr(q), _ptr(offs), None, 0)
+    rc = lib.oracle_probe_matches(len(kR), _ptr(kR), _ptr(kS), len(q), _ptr(q), _ptr(offs), None, 0,
+                                  int(threads))
     if rc < 0:
         raise MemoryError("oracle_probe_matches")
     ids = np.zeros(max(int(offs[-1]), 1), dtype=np.uint32)
     rc = lib.oracle_probe_matches(len(kR), _ptr(kR), _ptr(kS), len(q), _ptr(q), _ptr(offs),
-                                  _ptr(ids), int(offs[-1]))
+                                  _ptr(ids), int(offs[-1]), int(threads))
     if rc != 0:
         raise RuntimeError(f"oracle_probe_matches rc={rc}")
     return offs, ids[: int(offs[-1])]

@@ -42,7 +42,79 @@ static int cmp_u64(const void *a, const void *b)
     return x < y ? -1 : (x > y ? 1 : 0);
 }
 
-static keyed_row *sorted_rows(int64_t n, const int64_t *keys)
+/*
+ * Sort n elements of `size` bytes ascending by `cmp` with up to `threads`
+ * threads: each thread sorts one contiguous slice with qsort, then neighbouring
+ * sorted runs are merged pairwise (ties taken from the left run first) until
+ * one run remains. The result is the same ascending order qsort gives (the
+ * comparators below are total orders, so the sorted array is unique); only the
+ * time differs. Returns -1 if the merge buffer cannot be allocated.
+ */
+static void merge_runs(const char *src, size_t lo, size_t mid, size_t hi, char *dst, size_t size,
+                       int (*cmp)(const void *, const void *))
+{
+    size_t a = lo, b = mid, o = lo;
+    while (a < mid && b < hi) {
+        if (cmp(src + b * size, src + a * size) < 0) {
+            memcpy(dst + o * size, src + b * size, size);
+            ++b;
+        } else {
+            memcpy(dst + o * size, src + a * size, size);
+            ++a;
+        }
+        ++o;
+    }
+    if (a < mid) memcpy(dst + o * size, src + a * size, (mid - a) * size);
+    if (b < hi) memcpy(dst + o * size + (mid - a) * size, src + b * size, (hi - b) * size);
+}
+
+static int par_sort(void *base, size_t n, size_t size, int (*cmp)(const void *, const void *), int threads)
+{
+    if (threads < 2 || n < ((size_t)1 << 16)) {
+        qsort(base, n, size, cmp);
+        return 0;
+    }
+    const int t = threads;
+    size_t *bounds = (size_t *)malloc((size_t)(t + 1) * sizeof(size_t));
+    char *tmp = (char *)malloc(n * size);
+    if (!bounds || !tmp) {
+        free(bounds);
+        free(tmp);
+        return -1;
+    }
+    for (int i = 0; i <= t; ++i) bounds[i] = n * (size_t)i / (size_t)t;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(t) schedule(static, 1)
+#endif
+    for (int i = 0; i < t; ++i)
+        qsort((char *)base + bounds[i] * size, bounds[i + 1] - bounds[i], size, cmp);
+    char *src = (char *)base, *dst = tmp;
+    int runs = t;
+    while (runs > 1) {
+        const int pairs = runs / 2;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(t) schedule(static, 1)
+#endif
+        for (int r = 0; r < pairs; ++r)
+            merge_runs(src, bounds[2 * r], bounds[2 * r + 1], bounds[2 * r + 2], dst, size, cmp);
+        if (runs % 2)
+            memcpy(dst + bounds[runs - 1] * size, src + bounds[runs - 1] * size,
+                   (bounds[runs] - bounds[runs - 1]) * size);
+        const int next = (runs + 1) / 2;
+        for (int i = 0; i < next; ++i) bounds[i] = bounds[2 * i];
+        bounds[next] = n;
+        runs = next;
+        char *sw = src;
+        src = dst;
+        dst = sw;
+    }
+    if (src != (char *)base) memcpy(base, src, n * size);
+    free(tmp);
+    free(bounds);
+    return 0;
+}
+
+static keyed_row *sorted_rows(int64_t n, const int64_t *keys, int threads)
 {
     keyed_row *r = (keyed_row *)malloc((size_t)(n > 0 ? n : 1) * sizeof(keyed_row));
     if (!r) return NULL;
@@ -50,7 +122,10 @@ static keyed_row *sorted_rows(int64_t n, const int64_t *keys)
         r[i].key = keys[i];
         r[i].id = (uint32_t)i;
     }
-    qsort(r, (size_t)n, sizeof(keyed_row), cmp_keyed_row);
+    if (par_sort(r, (size_t)n, sizeof(keyed_row), cmp_keyed_row, threads) != 0) {
+        free(r);
+        return NULL;
+    }
     return r;
 }
 
@@ -60,16 +135,17 @@ static keyed_row *sorted_rows(int64_t n, const int64_t *keys)
  * on a run of equal keys emit the cross product of the two runs.
  *
  * pairs: NULL (count and checksum only) or room for `cap` u64 packed pairs.
+ * threads: threads for the sorts (par_sort); the merge walk is sequential.
  * Returns 0 on success, 1 if pairs was given and count > cap (the first cap
  * pairs found are written, not canonically), -1 on allocation failure.
  */
 int oracle_join_sortmerge(int64_t nR, const int64_t *kR, const int64_t *pR,
                           int64_t nS, const int64_t *kS, const int64_t *pS,
-                          uint64_t *pairs, int64_t cap,
+                          uint64_t *pairs, int64_t cap, int threads,
                           int64_t *count_out, int64_t *checksum_out)
 {
-    keyed_row *A = sorted_rows(nR, kR);
-    keyed_row *B = sorted_rows(nS, kS);
+    keyed_row *A = sorted_rows(nR, kR, threads);
+    keyed_row *B = sorted_rows(nS, kS, threads);
     if (!A || !B) {
         free(A);
         free(B);
@@ -101,7 +177,8 @@ int oracle_join_sortmerge(int64_t nR, const int64_t *kR, const int64_t *pR,
     }
     free(A);
     free(B);
-    if (pairs) qsort(pairs, (size_t)(count < cap ? count : cap), sizeof(uint64_t), cmp_u64);
+    if (pairs && par_sort(pairs, (size_t)(count < cap ? count : cap), sizeof(uint64_t), cmp_u64, threads) != 0)
+        return -1;
     *count_out = count;
     *checksum_out = (int64_t)checksum;
     return (pairs && count > cap) ? 1 : 0;
@@ -122,7 +199,7 @@ int oracle_join_totals(int64_t nR, const int64_t *kR, const int64_t *pR,
                        int64_t nS, const int64_t *kS, const int64_t *pS,
                        int threads, int64_t *count_out, int64_t *checksum_out)
 {
-    keyed_row *A = sorted_rows(nR, kR);
+    keyed_row *A = sorted_rows(nR, kR, threads);
     if (!A) return -1;
     int64_t nd = 0;
     int64_t *dkey = (int64_t *)malloc((size_t)(nR > 0 ? nR : 1) * sizeof(int64_t));
@@ -175,9 +252,9 @@ int oracle_join_totals(int64_t nR, const int64_t *kR, const int64_t *pR,
  */
 int oracle_probe_matches(int64_t nR, const int64_t *kR, const int64_t *kS,
                          int64_t nq, const int64_t *q, int64_t *offs,
-                         uint32_t *ids, int64_t cap)
+                         uint32_t *ids, int64_t cap, int threads)
 {
-    keyed_row *A = sorted_rows(nR, kR);
+    keyed_row *A = sorted_rows(nR, kR, threads);
     if (!A) return -1;
     int64_t total = 0;
     offs[0] = 0;

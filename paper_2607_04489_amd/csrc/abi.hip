@@ -375,20 +375,15 @@ extern "C" int eiger_join_workspace_size(const eiger_plan_t *plan, eiger_column 
   return EIGER_OK;
 }
 
-extern "C" int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column probe_keys,
-                          eiger_column probe_payload, const eiger_plan_t *plan, uint32_t *out_build_rowid,
-                          uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
-                          int64_t *out_checksum, void *ws_ptr, size_t ws_bytes, void *stream) {
-  int rc = check_join_inputs(build_keys, build_payload, probe_keys, probe_payload, plan);
-  if (rc) return rc;
-  if (!out_count || !out_checksum) return fail(EIGER_ERR_INVALID_ARG, "eiger_join: out_count/out_checksum is NULL");
-  if (out_capacity < 0) return fail(EIGER_ERR_INVALID_ARG, "eiger_join: negative out_capacity");
-  if ((out_build_rowid == nullptr) != (out_probe_rowid == nullptr))
-    return fail(EIGER_ERR_INVALID_ARG, "eiger_join: give both output arrays or neither");
-  if (out_capacity > 0 && !out_build_rowid)
-    return fail(EIGER_ERR_INVALID_ARG, "eiger_join: out_capacity > 0 with NULL output arrays");
-  JoinArgs a = make_args(build_keys, build_payload, probe_keys, probe_payload, plan, out_build_rowid,
-                         out_probe_rowid, out_capacity, stream);
+namespace eiger {
+
+// eiger_join with the argument checks done: sizes the plan's workspace, runs
+// the variant in (ws_ptr, ws_bytes), reads the counters back.
+int join_checked(const eiger_column &bk, const eiger_column &bp, const eiger_column &pk, const eiger_column &pp,
+                 const eiger_plan_t *plan, uint32_t *ob, uint32_t *op, int64_t cap, int64_t *out_count,
+                 int64_t *out_checksum, void *ws_ptr, size_t ws_bytes, void *stream) {
+  JoinArgs a = make_args(bk, bp, pk, pp, plan, ob, op, cap, stream);
+  int rc;
   {
     Workspace dry(nullptr, 0);
     JoinCounters *unused = nullptr;
@@ -407,8 +402,35 @@ extern "C" int eiger_join(eiger_column build_keys, eiger_column build_payload, e
     return fail(EIGER_ERR_INVALID_ARG, "eiger_join: a build key lies outside the plan's [build_min, build_max]");
   *out_count = static_cast<int64_t>(host.count);
   *out_checksum = static_cast<int64_t>(host.checksum);
-  if (out_build_rowid && host.count > static_cast<uint64_t>(out_capacity))
+  if (ob && host.count > static_cast<uint64_t>(cap))
     return fail(EIGER_ERR_CAPACITY, "eiger_join: " + std::to_string(host.count) +
-                                        " result pairs exceed out_capacity " + std::to_string(out_capacity));
+                                        " result pairs exceed out_capacity " + std::to_string(cap));
   return EIGER_OK;
+}
+
+// Checks shared by the join entry points (everything but the workspace).
+int check_join_call(const eiger_column &bk, const eiger_column &bp, const eiger_column &pk, const eiger_column &pp,
+                    const eiger_plan_t *plan, uint32_t *ob, uint32_t *op, int64_t cap, int64_t *out_count,
+                    int64_t *out_checksum) {
+  int rc = check_join_inputs(bk, bp, pk, pp, plan);
+  if (rc) return rc;
+  if (!out_count || !out_checksum) return fail(EIGER_ERR_INVALID_ARG, "eiger_join: out_count/out_checksum is NULL");
+  if (cap < 0) return fail(EIGER_ERR_INVALID_ARG, "eiger_join: negative out_capacity");
+  if ((ob == nullptr) != (op == nullptr))
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_join: give both output arrays or neither");
+  if (cap > 0 && !ob) return fail(EIGER_ERR_INVALID_ARG, "eiger_join: out_capacity > 0 with NULL output arrays");
+  return EIGER_OK;
+}
+
+}  // namespace eiger
+
+extern "C" int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column probe_keys,
+                          eiger_column probe_payload, const eiger_plan_t *plan, uint32_t *out_build_rowid,
+                          uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
+                          int64_t *out_checksum, void *ws_ptr, size_t ws_bytes, void *stream) {
+  int rc = check_join_call(build_keys, build_payload, probe_keys, probe_payload, plan, out_build_rowid,
+                           out_probe_rowid, out_capacity, out_count, out_checksum);
+  if (rc) return rc;
+  return join_checked(build_keys, build_payload, probe_keys, probe_payload, plan, out_build_rowid, out_probe_rowid,
+                      out_capacity, out_count, out_checksum, ws_ptr, ws_bytes, stream);
 }

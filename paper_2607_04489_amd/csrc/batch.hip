@@ -186,17 +186,18 @@ template <typename K, typename P>
 struct BatchHashTab {
   static constexpr bool kHashed = true;
   using SlotT = Slot<K, P>;
+  using Index = uint64_t;
   const Slot<K, P> *slots;
   uint64_t mask;
   bool unique;
-  __device__ __forceinline__ uint32_t home(K key) const {
-    return static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) & mask);
+  __device__ __forceinline__ uint64_t home(K key) const {
+    return fmix64(static_cast<uint64_t>(sext(key))) & mask;
   }
-  __device__ __forceinline__ uint32_t next(uint32_t i) const { return static_cast<uint32_t>((i + 1) & mask); }
-  __device__ __forceinline__ SlotT load(uint32_t i) const { return slots[i]; }
+  __device__ __forceinline__ uint64_t next(uint64_t i) const { return (i + 1) & mask; }
+  __device__ __forceinline__ SlotT load(uint64_t i) const { return slots[i]; }
   template <class F>
   __device__ __forceinline__ void for_each(K key, F f) const {
-    uint32_t i = home(key);
+    uint64_t i = home(key);
     for (;;) {
       const SlotT s = slots[i];
       if (s.rowid == kEmpty) break;

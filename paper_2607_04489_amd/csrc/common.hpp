@@ -39,12 +39,13 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask) {
                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0u));
 }
 
-// Inclusive wave64 scan of a u32 value with shuffles.
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+// Inclusive wave64 scan with shuffles (T = uint32_t or uint64_t).
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
   const int lane = __lane_id();
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    uint32_t t = __shfl_up(v, d, 64);
+    T t = __shfl_up(v, d, 64);
     if (lane >= d) v += t;
   }
   return v;
@@ -74,29 +75,29 @@ __device__ __forceinline__ int64_t wave_max_i64(int64_t v) {
   return v;
 }
 
-// Exclusive scan over a workgroup of NT threads. `scratch` must hold NT/64 + 1
-// u32 in LDS. Returns this thread's exclusive prefix; *total gets the sum.
-// Contains __syncthreads(): every thread of the workgroup must call it.
-template <int NT>
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *scratch,
-                                                         uint32_t *total) {
+// Exclusive scan over a workgroup of NT threads (T = uint32_t or uint64_t).
+// `scratch` must hold NT/64 + 1 values of T in LDS. Returns this thread's
+// exclusive prefix; *total gets the sum. Contains __syncthreads(): every
+// thread of the workgroup must call it.
+template <int NT, typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *scratch, T *total) {
   constexpr int NW = NT / 64;
   const int lane = __lane_id();
   const int wave = threadIdx.x / 64;
-  uint32_t inc = wave_inclusive_scan(v);
+  T inc = wave_inclusive_scan<T>(v);
   if (lane == 63) scratch[wave] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t run = 0;
+    T run = 0;
     for (int w = 0; w < NW; ++w) {
-      uint32_t t = scratch[w];
+      T t = scratch[w];
       scratch[w] = run;
       run += t;
     }
     scratch[NW] = run;
   }
   __syncthreads();
-  uint32_t r = scratch[wave] + inc - v;
+  T r = scratch[wave] + inc - v;
   *total = scratch[NW];
   __syncthreads();
   return r;

@@ -36,7 +36,7 @@ template <int NT, int SCAP>
 struct EmitLds {
   uint32_t b[SCAP];
   uint32_t p[SCAP];
-  uint32_t scan[NT / 64 + 1];
+  uint64_t scan[NT / 64 + 1];
   uint64_t base;
   uint64_t red[NT / 64];
 };
@@ -50,7 +50,7 @@ __device__ __forceinline__ void put_pair(const EmitOut &o, uint64_t pos, uint32_
 
 // Reserve `count` output slots for the whole workgroup; all threads get the base.
 template <int NT, int SCAP>
-__device__ __forceinline__ uint64_t reserve(EmitLds<NT, SCAP> &L, const EmitOut &o, uint32_t count) {
+__device__ __forceinline__ uint64_t reserve(EmitLds<NT, SCAP> &L, const EmitOut &o, uint64_t count) {
   if (threadIdx.x == 0) L.base = atomicAdd(reinterpret_cast<unsigned long long *>(o.cursor),
                                            static_cast<unsigned long long>(count));
   __syncthreads();
@@ -116,8 +116,9 @@ __device__ __forceinline__ void probe_load(ProbeRegs<IPT, K, PS> &r, const K *__
 }
 
 // Count the matches of every loaded row. Tables of two kinds:
-//  * hashed tables (Tab::kHashed) expose home(key), next(i), load(i) -> slot
-//    and a `unique` flag (build keys known to be distinct). The first slot of
+//  * hashed tables (Tab::kHashed) expose an index type Index, home(key),
+//    next(i), load(i) -> slot and a `unique` flag (build keys known to be
+//    distinct). The first slot of
 //    every row is loaded before any is inspected, so a thread keeps IPT random
 //    loads in flight; only rows whose walk is not finished load again, and a
 //    unique table stops a walk at its first match.
@@ -134,7 +135,7 @@ __device__ __forceinline__ void count_matches(const Tab &tab, const ProbeRegs<IP
     psum[k] = 0;
   }
   if constexpr (Tab::kHashed) {
-    uint32_t idx[IPT];
+    typename Tab::Index idx[IPT];
     typename Tab::SlotT sl[IPT];
     bool live[IPT];
 #pragma unroll
@@ -196,7 +197,8 @@ __device__ __forceinline__ void count_matches(const Tab &tab, const ProbeRegs<IP
 
 // Probe the loaded rows against `tab` and materialize the matches. Tables also
 // provide  template <class F> void for_each(K key, F f) const  (f(build_rowid)
-// for every match) for rows with more than one match.
+// for every match) for rows with more than one match. Match totals are 64-bit:
+// a sub-tile of rows that each meet billions of build rows does not wrap.
 // Uniform across the workgroup (contains barriers).
 template <int NT, int IPT, int SCAP, class Tab, typename K, typename PS>
 __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IPT, K, PS> &r,
@@ -205,14 +207,14 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
   uint32_t cnt[IPT], first[IPT];
   uint64_t psum[IPT];
   count_matches<NT, IPT>(tab, r, cnt, first, psum);
-  uint32_t mine = 0;
+  uint64_t mine = 0;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     if (cnt[k]) cs += psum[k] * static_cast<uint64_t>(sext(r.pay[k]));
     mine += cnt[k];
   }
-  uint32_t total;
-  const uint32_t off = block_exclusive_scan<NT>(mine, L.scan, &total);
+  uint64_t total;
+  const uint64_t off = block_exclusive_scan<NT, uint64_t>(mine, L.scan, &total);
   if (total == 0) return;
   if (!o.ob) {  // count-only: no positions are needed, so nothing is reserved
     fill += total;
@@ -233,8 +235,8 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     uint64_t done = 0;  // pairs of this sub-tile placed so far (uniform)
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
-      uint32_t tk;
-      const uint32_t ok = block_exclusive_scan<NT>(cnt[k], L.scan, &tk);
+      uint64_t tk;
+      const uint64_t ok = block_exclusive_scan<NT, uint64_t>(cnt[k], L.scan, &tk);
       if (tk == 0) continue;
       if (tk > SCAP) {
         uint64_t pos = base + done + ok;
@@ -247,7 +249,7 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
         done += tk;
         continue;
       }
-      uint32_t pos = ok;
+      uint32_t pos = static_cast<uint32_t>(ok);
       if (cnt[k] == 1) {
         L.b[pos] = first[k];
         L.p[pos] = r.rid[k];
@@ -264,10 +266,9 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
       __syncthreads();
       done += tk;
     }
-    (void)off;
     return;
   }
-  uint32_t pos = static_cast<uint32_t>(fill) + off;
+  uint32_t pos = static_cast<uint32_t>(fill + off);
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     if (cnt[k] == 1) {

@@ -24,20 +24,21 @@ template <typename K, typename PB>
 struct HashTab {
   static constexpr bool kHashed = true;
   using SlotT = Slot<K, PB>;
+  using Index = uint64_t;  // a table may hold more than 2^32 slots
   const Slot<K, PB> *__restrict__ slots;
   uint64_t mask;
   const uint32_t *dup;  // device flag: nonzero when some build key occurs twice
   bool unique;          // set in the kernel from *dup
 
   __device__ __forceinline__ void init() { unique = dup && *dup == 0; }
-  __device__ __forceinline__ uint32_t home(K key) const {
-    return static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) & mask);
+  __device__ __forceinline__ uint64_t home(K key) const {
+    return fmix64(static_cast<uint64_t>(sext(key))) & mask;
   }
-  __device__ __forceinline__ uint32_t next(uint32_t i) const { return static_cast<uint32_t>((i + 1) & mask); }
-  __device__ __forceinline__ SlotT load(uint32_t i) const { return slots[i]; }
+  __device__ __forceinline__ uint64_t next(uint64_t i) const { return (i + 1) & mask; }
+  __device__ __forceinline__ SlotT load(uint64_t i) const { return slots[i]; }
   template <class F>
   __device__ __forceinline__ void for_each(K key, F f) const {
-    uint32_t i = home(key);
+    uint64_t i = home(key);
     for (;;) {
       const Slot<K, PB> s = slots[i];
       if (s.rowid == kEmpty) break;

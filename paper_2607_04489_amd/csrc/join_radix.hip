@@ -552,8 +552,8 @@ __device__ __forceinline__ void join_chunk_grouped(const int32_t *__restrict__ r
     const uint32_t lo = min(ns, threadIdx.x * per), hi = min(ns, lo + per);
     uint32_t local = 0;
     for (uint32_t i = lo; i < hi; ++i) local += static_cast<uint32_t>(W[i] & 0xFFFFu);
-    uint32_t tot;
-    uint32_t run = block_exclusive_scan<kJNT>(local, L.scan, &tot);
+    uint64_t tot;
+    uint32_t run = static_cast<uint32_t>(block_exclusive_scan<kJNT, uint64_t>(local, L.scan, &tot));
     for (uint32_t i = lo; i < hi; ++i) {
       const unsigned long long v = W[i];
       W[i] = (v & 0xFFFFFFFF0000FFFFull) | (static_cast<unsigned long long>(run) << 16);
@@ -913,6 +913,7 @@ template <typename K, typename PB>
 struct CacheTab {
   static constexpr bool kHashed = true;
   using SlotT = Slot<K, PB>;
+  using Index = uint32_t;  // regions hold fewer than 2^32 slots
   const Slot<K, PB> *__restrict__ slots;
   uint32_t n;
   bool unique;

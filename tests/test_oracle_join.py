@@ -188,3 +188,26 @@ def test_planted_mistake_is_caught():
     bad = pairs.copy()
     bad[3] += np.uint64(1)
     assert not np.array_equal(np.sort(bad), bp)
+
+
+@pytest.mark.parametrize("threads", [2, 5, 16])
+def test_threaded_sorts_match_one_thread(threads):
+    """The threaded slice sort + pairwise merges (an odd slice count leaves one
+    run to copy through) give the same pairs, count and checksum as one thread,
+    on inputs large enough to take the threaded path (>= 2^16 rows per side),
+    with heavy duplicates so that equal keys cross slice boundaries; the pairs
+    are also checked against numpy's own canonical order of the same set."""
+    inp = synth.random_small(21, 70000, 90000, 0, 3000)
+    one = oracle.join_sortmerge(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload)
+    many = oracle.join_sortmerge(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload,
+                                 threads=threads)
+    assert one[1:] == many[1:]
+    assert np.array_equal(one[0], many[0])
+    assert np.array_equal(many[0], np.sort(many[0]))
+    rows = np.arange(0, 90000, 997, dtype=np.int64)
+    o1, i1 = oracle.probe_matches(inp.build_keys, inp.probe_keys, rows)
+    o2, i2 = oracle.probe_matches(inp.build_keys, inp.probe_keys, rows, threads=threads)
+    assert np.array_equal(o1, o2) and np.array_equal(i1, i2)
+    kR, kS = inp.build_keys.numpy(), inp.probe_keys.numpy()
+    for t, j in enumerate(rows[:20]):
+        assert i2[o2[t]:o2[t + 1]].tolist() == np.nonzero(kR == kS[j])[0].tolist()
