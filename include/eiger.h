@@ -22,8 +22,9 @@
  *    synchronize the stream before returning.
  *  - Every call returns an eiger_status; on failure eiger_last_error() holds
  *    a message for the calling thread. No C++ exception crosses the ABI.
- *  - Row ids are uint32: a column may hold at most 2^32 - 1 rows
- *    (EIGER_ERR_TOO_LARGE beyond that). Counts and sizes are int64.
+ *  - Row ids are uint32: a column may hold at most EIGER_MAX_ROWS =
+ *    2^32 - 2^16 rows (EIGER_ERR_TOO_LARGE beyond that; the margin keeps the
+ *    kernels' 32-bit tile bounds from wrapping). Counts and sizes are int64.
  *  - Calls on different streams may run concurrently when each has its own
  *    workspace and outputs.
  */
@@ -41,7 +42,7 @@ typedef enum {
     EIGER_OK = 0,
     EIGER_ERR_INVALID_ARG = -1, /* null pointer, negative size, bad enum value */
     EIGER_ERR_DTYPE = -2,       /* unsupported dtype or key dtypes that differ */
-    EIGER_ERR_TOO_LARGE = -3,   /* more than 2^32 - 1 rows, or a table beyond its limit */
+    EIGER_ERR_TOO_LARGE = -3,   /* more than EIGER_MAX_ROWS rows, or a table beyond its limit */
     EIGER_ERR_CAPACITY = -4,    /* output capacity below the result size; count is set */
     EIGER_ERR_WORKSPACE = -5,   /* ws_bytes below the size the *_workspace_size call gives */
     EIGER_ERR_HIP = -6,         /* a HIP runtime call failed (message has the HIP error) */
@@ -50,6 +51,9 @@ typedef enum {
 } eiger_status;
 
 typedef enum { EIGER_INT32 = 0, EIGER_INT64 = 1 } eiger_dtype;
+
+/* Most rows a column (or one side of a batched join) may hold: 2^32 - 2^16. */
+#define EIGER_MAX_ROWS 4294901760LL
 
 /* A column: `n` values of `dtype` at DEVICE address `data` (may be NULL when n == 0). */
 typedef struct {

@@ -118,8 +118,8 @@ int check_column(const eiger_column &c, const char *what, bool key) {
   if (c.dtype != EIGER_INT32 && c.dtype != EIGER_INT64)
     return fail(EIGER_ERR_DTYPE, std::string(what) + ": dtype must be EIGER_INT32 or EIGER_INT64");
   if (c.n < 0) return fail(EIGER_ERR_INVALID_ARG, std::string(what) + ": negative row count");
-  if (c.n > 0xFFFFFFFELL)
-    return fail(EIGER_ERR_TOO_LARGE, std::string(what) + ": more than 2^32-1 rows (row ids are uint32)");
+  if (c.n > EIGER_MAX_ROWS)
+    return fail(EIGER_ERR_TOO_LARGE, std::string(what) + ": more than EIGER_MAX_ROWS = 2^32 - 2^16 rows");
   if (c.n > 0 && !c.data) return fail(EIGER_ERR_INVALID_ARG, std::string(what) + ": data is NULL");
   if (c.n > 0 && reinterpret_cast<uintptr_t>(c.data) % dtype_size(c.dtype) != 0)
     return fail(EIGER_ERR_INVALID_ARG, std::string(what) + ": data is not aligned to its dtype");

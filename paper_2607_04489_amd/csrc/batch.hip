@@ -268,8 +268,8 @@ int plan_batch(const eiger_batch_join *joins, int32_t n, int32_t kdt, int32_t pd
   for (int32_t j = 0; j < n; ++j) {
     const eiger_batch_join &q = joins[j];
     if (q.n_build < 0 || q.n_probe < 0) return fail(EIGER_ERR_INVALID_ARG, "batch: negative row count");
-    if (q.n_build > 0xFFFFFFFELL || q.n_probe > 0xFFFFFFFELL)
-      return fail(EIGER_ERR_TOO_LARGE, "batch: a join has more than 2^32-1 rows");
+    if (q.n_build > EIGER_MAX_ROWS || q.n_probe > EIGER_MAX_ROWS)
+      return fail(EIGER_ERR_TOO_LARGE, "batch: a join side has more than EIGER_MAX_ROWS = 2^32 - 2^16 rows");
     if ((q.n_build > 0 && (!q.build_keys || !q.build_payload)) || (q.n_probe > 0 && (!q.probe_keys || !q.probe_payload)))
       return fail(EIGER_ERR_INVALID_ARG, "batch: NULL column of a non-empty side");
     const size_t ks = dtype_size(kdt), ps = dtype_size(pdt);

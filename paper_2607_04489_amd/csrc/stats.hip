@@ -262,7 +262,8 @@ extern "C" int eiger_stats(eiger_column keys, eiger_stats_t *out, uint8_t *hll_r
   if (keys.dtype != EIGER_INT32 && keys.dtype != EIGER_INT64)
     return fail(EIGER_ERR_DTYPE, "eiger_stats: key dtype must be EIGER_INT32 or EIGER_INT64");
   if (keys.n < 0) return fail(EIGER_ERR_INVALID_ARG, "eiger_stats: negative row count");
-  if (keys.n > 0xFFFFFFFELL) return fail(EIGER_ERR_TOO_LARGE, "eiger_stats: more than 2^32-1 rows");
+  if (keys.n > EIGER_MAX_ROWS)
+    return fail(EIGER_ERR_TOO_LARGE, "eiger_stats: more than EIGER_MAX_ROWS = 2^32 - 2^16 rows");
   if (keys.n > 0 && !keys.data) return fail(EIGER_ERR_INVALID_ARG, "eiger_stats: keys.data is NULL");
   if (keys.n > 0 && (reinterpret_cast<uintptr_t>(keys.data) % dtype_size(keys.dtype)) != 0)
     return fail(EIGER_ERR_INVALID_ARG, "eiger_stats: keys.data is not aligned to its dtype");

@@ -261,3 +261,29 @@ def test_batch_host_checks(lib):
 
 def test_batch_bucket():
     assert [eg.batch_bucket(n) for n in (0, 1, 2, 3, 4, 255, 256, 1 << 20)] == [0, 0, 1, 1, 2, 7, 8, 20]
+
+
+MAX_ROWS = (1 << 32) - (1 << 16)
+
+
+def test_row_limit_is_eiger_max_rows(lib):
+    """A column may hold EIGER_MAX_ROWS = 2^32 - 2^16 rows; one more is
+    EIGER_ERR_TOO_LARGE (the join's sizing, the join and the statistics)."""
+    b = stats(MAX_ROWS, -(1 << 40), 1 << 40, float(MAX_ROWS), eg.INT64)
+    ok = col(4096, MAX_ROWS, eg.INT64)
+    over = col(4096, MAX_ROWS + 1, eg.INT64)
+    half = col(4096, 1 << 31, eg.INT64)  # RADIX_CACHE's one table stays below 2^32 slots
+    size = ctypes.c_size_t()
+    for v, bits, passes, r in [(eg.GLOBAL_HASH, 0, 0, ok), (eg.RADIX, 16, 2, ok), (eg.RADIX_CACHE, 10, 1, half)]:
+        p = plan(b, b, eg.SEL_FORCED, eg.make_plan(v, bits, passes, 0.9 if v == eg.RADIX_CACHE else 0.5))
+        assert lib.eiger_join_workspace_size(ctypes.byref(p), r, r, ok, ok, ctypes.byref(size)) == 0, \
+            eg.lib().eiger_last_error()
+        assert size.value > 16 * MAX_ROWS
+        assert lib.eiger_join_workspace_size(ctypes.byref(p), over, over, ok, ok,
+                                             ctypes.byref(size)) == eg.EIGER_ERR_TOO_LARGE
+        assert lib.eiger_join_workspace_size(ctypes.byref(p), r, r, over, over,
+                                             ctypes.byref(size)) == eg.EIGER_ERR_TOO_LARGE
+    out = eg.StatsT()
+    assert lib.eiger_stats(col(4096, MAX_ROWS + 1, eg.INT32), ctypes.byref(out), None, None, 0,
+                           None) == eg.EIGER_ERR_TOO_LARGE
+
