@@ -194,6 +194,28 @@ int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column
                uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
                int64_t *out_checksum, void *ws, size_t ws_bytes, void *stream);
 
+/* Bytes of the fixed device scratch array behind eiger_join_noalloc (64 MiB). */
+#define EIGER_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/*
+ * eiger_join for callers that cannot allocate device memory (code under HIP
+ * graph capture setup, tight serving loops, hosts that forbid hipMalloc): the
+ * same join, arguments and results, but its scratch memory is a fixed array of
+ * EIGER_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until the
+ * process ends) instead of a caller workspace. The library allocates nothing.
+ * The caller still passes inputs and DEVICE outputs.
+ *  - Returns EIGER_ERR_TOO_LARGE, before any GPU work, when the plan's
+ *    workspace (eiger_join_workspace_size) exceeds EIGER_NOALLOC_SCRATCH_BYTES.
+ *  - `stream` must belong to the current device (EIGER_ERR_INVALID_ARG otherwise).
+ *  - All calls on one GPU share its array: calls that overlap in time on one GPU
+ *    (different streams or threads) race and must be serialized by the caller.
+ * Synchronizes `stream`.
+ */
+int eiger_join_noalloc(eiger_column build_keys, eiger_column build_payload, eiger_column probe_keys,
+                       eiger_column probe_payload, const eiger_plan_t *plan, uint32_t *out_build_rowid,
+                       uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
+                       int64_t *out_checksum, void *stream);
+
 /* ---- batched joins: many independent joins in one graph launch -----------------
  * Every join of a batch runs the same path (statistics of the build keys ->
  * per-join variant choice on the device -> build -> probe -> materialize) with

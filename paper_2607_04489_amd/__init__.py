@@ -111,6 +111,9 @@ def lib():
         L.eiger_join.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                  ctypes.POINTER(i64), ctypes.POINTER(i64), vp, sz, vp]
         L.eiger_join.restype = ctypes.c_int
+        L.eiger_join_noalloc.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
+                                         ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
+        L.eiger_join_noalloc.restype = ctypes.c_int
         L.eiger_last_error.argtypes = []
         L.eiger_last_error.restype = ctypes.c_char_p
         L.eiger_version.restype = ctypes.c_int
@@ -288,6 +291,32 @@ def join(bk, bp, pk, pp, plan: PlanT, capacity: Optional[int] = None, stream=Non
         op = torch.empty(capacity, dtype=torch.int32, device=pk.device)
         rc = run(ob, op, capacity)
     _check(rc, cnt.value)
+    return JoinResult(ob[: cnt.value], op[: cnt.value], cnt.value, cs.value)
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def join_noalloc(bk, bp, pk, pp, plan: PlanT, outputs=None, stream=None) -> JoinResult:
+    """eiger_join_noalloc: the join with the library's fixed scratch array as its
+    workspace. `outputs` = (out_b, out_p) device int32 tensors, or None for
+    count-only mode. Raises EigerError (code EIGER_ERR_CAPACITY with .count set
+    when the outputs are too small)."""
+    cols = [column(t) for t in (bk, bp, pk, pp)]
+    cnt, cs = ctypes.c_int64(), ctypes.c_int64()
+    if outputs is None:
+        ob = op = None
+        cap = 0
+    else:
+        ob, op = outputs
+        cap = min(ob.numel(), op.numel())
+    rc = lib().eiger_join_noalloc(*cols, ctypes.byref(plan),
+                                  ctypes.c_void_p(ob.data_ptr()) if ob is not None else None,
+                                  ctypes.c_void_p(op.data_ptr()) if op is not None else None,
+                                  cap, ctypes.byref(cnt), ctypes.byref(cs), _stream_ptr(stream))
+    _check(rc, cnt.value)
+    if ob is None:
+        return JoinResult(None, None, cnt.value, cs.value)
     return JoinResult(ob[: cnt.value], op[: cnt.value], cnt.value, cs.value)
 
 

@@ -356,13 +356,15 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
   return EIGER_OK;
 }
 
-extern "C" int eiger_join_workspace_size(const eiger_plan_t *plan, eiger_column build_keys,
-                                         eiger_column build_payload, eiger_column probe_keys,
-                                         eiger_column probe_payload, size_t *bytes) {
+namespace eiger {
+
+// Workspace bytes of a join (host only; the columns' data pointers are not read).
+int join_workspace_bytes(const eiger_column &bk, const eiger_column &bp, const eiger_column &pk,
+                         const eiger_column &pp, const eiger_plan_t *plan, size_t *bytes) {
   if (!bytes) return fail(EIGER_ERR_INVALID_ARG, "eiger_join_workspace_size: bytes is NULL");
   // sizing never reads data: give the checks a dummy aligned address
   static const int64_t dummy[1] = {0};
-  eiger_column cols[4] = {build_keys, build_payload, probe_keys, probe_payload};
+  eiger_column cols[4] = {bk, bp, pk, pp};
   for (auto &c : cols)
     if (c.n > 0) c.data = dummy;
   int rc = check_join_inputs(cols[0], cols[1], cols[2], cols[3], plan);
@@ -373,6 +375,14 @@ extern "C" int eiger_join_workspace_size(const eiger_plan_t *plan, eiger_column 
   if ((rc = run_variant(a, ws, &ctr))) return rc;
   *bytes = ws.used;
   return EIGER_OK;
+}
+
+}  // namespace eiger
+
+extern "C" int eiger_join_workspace_size(const eiger_plan_t *plan, eiger_column build_keys,
+                                         eiger_column build_payload, eiger_column probe_keys,
+                                         eiger_column probe_payload, size_t *bytes) {
+  return join_workspace_bytes(build_keys, build_payload, probe_keys, probe_payload, plan, bytes);
 }
 
 namespace eiger {

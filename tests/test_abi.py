@@ -287,3 +287,27 @@ def test_row_limit_is_eiger_max_rows(lib):
     assert lib.eiger_stats(col(4096, MAX_ROWS + 1, eg.INT32), ctypes.byref(out), None, None, 0,
                            None) == eg.EIGER_ERR_TOO_LARGE
 
+
+def test_noalloc_checks_before_any_gpu_work(lib):
+    """eiger_join_noalloc refuses, on the host, plans whose workspace exceeds its
+    fixed scratch array, and shares eiger_join's argument checks."""
+    cnt, cs = ctypes.c_int64(), ctypes.c_int64()
+    b = stats(10_000_000, -(1 << 40), 1 << 40, 1e7, eg.INT64)
+    p = plan(b, b, eg.SEL_FORCED, eg.make_plan(eg.GLOBAL_HASH, 0, 0, 0.5))
+    big = col(4096, 10_000_000, eg.INT64)
+    size = ctypes.c_size_t()
+    assert lib.eiger_join_workspace_size(ctypes.byref(p), big, big, big, big, ctypes.byref(size)) == 0
+    assert size.value > eg.NOALLOC_SCRATCH_BYTES
+    rc = lib.eiger_join_noalloc(big, big, big, big, ctypes.byref(p), None, None, 0, ctypes.byref(cnt),
+                                ctypes.byref(cs), None)
+    assert rc == eg.EIGER_ERR_TOO_LARGE
+    assert "scratch" in eg.lib().eiger_last_error().decode()
+    small = stats(10, 0, 9, 10.0)
+    ps = plan(small, small)
+    good = col(4096, 10, eg.INT32)
+    assert lib.eiger_join_noalloc(good, good, col(4096, 10, eg.INT64), col(4096, 10, eg.INT64), ctypes.byref(ps),
+                                  None, None, 0, ctypes.byref(cnt), ctypes.byref(cs), None) == eg.EIGER_ERR_DTYPE
+    assert lib.eiger_join_noalloc(good, good, good, good, ctypes.byref(ps), 4096, None, 10, ctypes.byref(cnt),
+                                  ctypes.byref(cs), None) == eg.EIGER_ERR_INVALID_ARG
+    assert lib.eiger_join_noalloc(good, good, good, good, ctypes.byref(ps), None, None, 0, None,
+                                  ctypes.byref(cs), None) == eg.EIGER_ERR_INVALID_ARG
