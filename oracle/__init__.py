@@ -8,6 +8,7 @@ Contents (each function cites the passage of the paper it follows):
   * join_sortmerge  -- the join result (pairs, count, checksum) by sort-merge
   * join_totals     -- count and checksum from per-key aggregates of R
   * probe_matches   -- matching build rows of sampled probe rows
+  * join_wide       -- the join result with both sides' payload columns materialized
   * column_stats    -- count, min, max, HLL registers and distinct estimate
   * fmix64          -- the 64-bit hash used by the sketch
 The C part lives in ``eiger_oracle.c`` and is compiled with gcc on first use.
@@ -218,6 +219,30 @@ def column_stats(keys, p: int = HLL_P) -> dict:
         return {"n": 0, "min": 0, "max": 0, "regs": regs, "ndv": 0.0}
     return {"n": int(k.size), "min": int(k.min()), "max": int(k.max()), "regs": regs,
             "ndv": hll_estimate(regs)}
+
+
+def _host(a) -> np.ndarray:
+    """Host copy of a column (torch tensor or array), dtype kept."""
+    if hasattr(a, "detach"):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(a))
+
+
+def join_wide(kR, colsR, kS, colsS, threads: int = 1):
+    """Wide inner equi-join: the join result with every payload column of both
+    relations materialized for each result pair (Section 5.2.1: the wide join,
+    tables of a key and several payload columns whose payloads must be
+    materialized; Section 3.2: GFUR and GFTR are two ways of producing this same
+    result, from the untransformed or from the transformed relations).
+
+    Plain definition: take the canonical pair list P of the inner equi-join
+    (join_sortmerge), then output column c of R at result row t is colsR[c][i_t]
+    and of S is colsS[c][j_t] for the t-th pair (i_t, j_t) of P, in the input
+    column's dtype. Returns (pairs, outR, outS)."""
+    pairs, _, _ = join_sortmerge(kR, kR, kS, kS, threads=threads)
+    i = (pairs >> np.uint64(32)).astype(np.int64)
+    j = (pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    return pairs, [_host(c)[i] for c in colsR], [_host(c)[j] for c in colsS]
 
 
 def canonical_pairs(build_rows, probe_rows) -> np.ndarray:

@@ -166,6 +166,38 @@ def plain_dense(seed: int = 42, n_build: int = 65536, n_probe: int = 1 << 20,
     )
 
 
+def wide_join(seed: int = 42, n_build: int = 1 << 16, n_probe: int = 1 << 28, match_per_mille: int = 1000,
+              n_cols: int = 3, key_dtype=torch.int32, col_dtype=torch.int32, device="cpu") -> JoinInput:
+    """Wide join (the paper's Section 5.2 wide-join and match-ratio workloads:
+    tables of a key and three payload columns, a smaller build side R with
+    unique keys and a larger probe side S). Build keys = a shuffle of
+    [0, n_build) spread by a factor 2 (key = 2 * index, so odd keys never
+    match); a probe row matches with probability match_per_mille / 1000 and then
+    copies a uniformly drawn build key, otherwise it takes an odd key. Payload
+    columns: n_cols per side, uniform over the column dtype's full range.
+    meta["build_cols"] / meta["probe_cols"] hold the payload columns
+    (build_payload / probe_payload are the first of them)."""
+    dev = torch.device(device)
+    ib = torch.arange(n_build, dtype=torch.int64, device=dev)
+    ip = torch.arange(n_probe, dtype=torch.int64, device=dev)
+    bk = 2 * permutation(seed, 1, n_build, dev)
+    hit = uniform_below(rand64(seed, 2, ip), 1000) < match_per_mille
+    src = uniform_below(rand64(seed, 3, ip), max(n_build, 1))
+    miss = 2 * uniform_below(rand64(seed, 4, ip), 1 << 30) + 1
+    pk = torch.where(hit, bk[src] if n_build else miss, miss)
+
+    def col(stream, idx):
+        r = rand64(seed, stream, idx)
+        return r if col_dtype == torch.int64 else (r >> 32).to(torch.int32)
+
+    bcols = [col(10 + c, ib) for c in range(n_cols)]
+    pcols = [col(20 + c, ip) for c in range(n_cols)]
+    return JoinInput(name=f"wide_{n_build}x{n_probe}_m{match_per_mille}", build_keys=bk.to(key_dtype),
+                     build_payload=bcols[0] if n_cols else bk.to(col_dtype), probe_keys=pk.to(key_dtype),
+                     probe_payload=pcols[0] if n_cols else pk.to(col_dtype),
+                     meta={"build_cols": bcols, "probe_cols": pcols, "match_per_mille": match_per_mille})
+
+
 def sparse_unique64(seed: int = 42, n_build: int = 1 << 24, n_probe: int = 1 << 29,
                     match_per_mille: int = 900, device="cpu") -> JoinInput:
     """Large sparse join: unique int64 build keys spread over the full 64-bit range,
@@ -413,38 +445,49 @@ def bij_bits(x: torch.Tensor, bits: int, seed: int) -> torch.Tensor:
     return x
 
 
-def batched_joins(seed: int, n_joins: int, log2_lo: float = 8.0, log2_hi: float = 18.0, device="cpu"):
-    """Independent unique-key int32 joins of uneven sizes: build rows
-    round(2^U(log2_lo, log2_hi)); probe rows = build rows * U[4, 16]; match rate
-    m ~ U[0.1, 1]. Even-indexed joins are dense: build keys = a shuffle of
-    [b, b + n) and probe keys U[b, b + n/m). Odd-indexed joins are sparse: build
-    keys = 2 * (a keyed bijection of their indices on [0, 2^30)), matching probe
-    rows copy a uniformly drawn build key, the others take odd keys 2v + 1.
-    Payloads U[0, 1000). Returns a list of JoinInput."""
+def batched_join_params(seed: int, j: int, log2_lo: float = 8.0, log2_hi: float = 18.0):
+    """Sizes of join j of a batch without drawing it: (build rows, probe rows,
+    match rate, dense). Build rows round(2^U(log2_lo, log2_hi)); probe rows =
+    build rows * U[4, 16]; match rate U[0.1, 1]; even joins dense."""
+    u = [_u01(seed, 500 + k, j) for k in range(4)]
+    nb = int(round(2.0 ** (log2_lo + u[0] * (log2_hi - log2_lo))))
+    npr = int(round(nb * (4.0 + 12.0 * u[1])))
+    m = 0.1 + 0.9 * u[2]
+    return nb, npr, m, j % 2 == 0
+
+
+def batched_join(seed: int, j: int, log2_lo: float = 8.0, log2_hi: float = 18.0, device="cpu") -> JoinInput:
+    """Join j of a batch of independent unique-key int32 joins of uneven sizes
+    (sizes from batched_join_params). Dense joins: build keys = a shuffle of
+    [b, b + n) and probe keys U[b, b + n/m). Sparse joins: build keys =
+    2 * (a keyed bijection of their indices on [0, 2^30)), matching probe rows
+    copy a uniformly drawn build key, the others take odd keys 2v + 1. Payloads
+    U[0, 1000). Each join depends only on (seed, j), so a batch can be drawn
+    in any order or in parts."""
     dev = torch.device(device)
-    out = []
-    for j in range(n_joins):
-        u = [_u01(seed, 500 + k, j) for k in range(4)]
-        nb = int(round(2.0 ** (log2_lo + u[0] * (log2_hi - log2_lo))))
-        npr = int(round(nb * (4.0 + 12.0 * u[1])))
-        m = 0.1 + 0.9 * u[2]
-        js = seed * 1000003 + j
-        ib = torch.arange(nb, dtype=torch.int64, device=dev)
-        ip = torch.arange(npr, dtype=torch.int64, device=dev)
-        if j % 2 == 0:
-            b = int(u[3] * (1 << 29))
-            bk = b + permutation(js, 1, nb, dev)
-            span = max(1, int(round(nb / m)))
-            pk = b + uniform_below(rand64(js, 2, ip), span)
-        else:
-            bk = 2 * bij_bits(ib, 30, js)
-            hit = uniform01(rand64(js, 3, ip)) < m
-            src = uniform_below(rand64(js, 4, ip), nb)
-            miss = 2 * uniform_below(rand64(js, 5, ip), 1 << 30) + 1
-            pk = torch.where(hit, bk[src], miss)
-        out.append(JoinInput(name=f"batch_{j}", build_keys=bk.to(torch.int32),
-                             build_payload=uniform_below(rand64(js, 6, ib), 1000).to(torch.int32),
-                             probe_keys=pk.to(torch.int32),
-                             probe_payload=uniform_below(rand64(js, 7, ip), 1000).to(torch.int32),
-                             meta={"dense": j % 2 == 0, "match": m}))
-    return out
+    nb, npr, m, dense = batched_join_params(seed, j, log2_lo, log2_hi)
+    u3 = _u01(seed, 503, j)
+    js = seed * 1000003 + j
+    ib = torch.arange(nb, dtype=torch.int64, device=dev)
+    ip = torch.arange(npr, dtype=torch.int64, device=dev)
+    if dense:
+        b = int(u3 * (1 << 29))
+        bk = b + permutation(js, 1, nb, dev)
+        span = max(1, int(round(nb / m)))
+        pk = b + uniform_below(rand64(js, 2, ip), span)
+    else:
+        bk = 2 * bij_bits(ib, 30, js)
+        hit = uniform01(rand64(js, 3, ip)) < m
+        src = uniform_below(rand64(js, 4, ip), nb)
+        miss = 2 * uniform_below(rand64(js, 5, ip), 1 << 30) + 1
+        pk = torch.where(hit, bk[src], miss)
+    return JoinInput(name=f"batch_{j}", build_keys=bk.to(torch.int32),
+                     build_payload=uniform_below(rand64(js, 6, ib), 1000).to(torch.int32),
+                     probe_keys=pk.to(torch.int32),
+                     probe_payload=uniform_below(rand64(js, 7, ip), 1000).to(torch.int32),
+                     meta={"dense": dense, "match": m})
+
+
+def batched_joins(seed: int, n_joins: int, log2_lo: float = 8.0, log2_hi: float = 18.0, device="cpu"):
+    """Joins 0 .. n_joins-1 of a batch (batched_join). Returns a list of JoinInput."""
+    return [batched_join(seed, j, log2_lo, log2_hi, device) for j in range(n_joins)]

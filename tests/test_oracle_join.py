@@ -211,3 +211,49 @@ def test_threaded_sorts_match_one_thread(threads):
     kR, kS = inp.build_keys.numpy(), inp.probe_keys.numpy()
     for t, j in enumerate(rows[:20]):
         assert i2[o2[t]:o2[t + 1]].tolist() == np.nonzero(kR == kS[j])[0].tolist()
+
+
+def wide_brute_force(kR, colsR, kS, colsS):
+    """Nested loops in (i, j) order: the result rows of the wide join."""
+    rows = []
+    for i in range(len(kR)):
+        for j in range(len(kS)):
+            if kR[i] == kS[j]:
+                rows.append((i, j, [int(c[i]) for c in colsR], [int(c[j]) for c in colsS]))
+    return rows
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_wide_join_vs_brute_force(seed):
+    """Wide join: canonical pairs and every materialized column equal the
+    nested-loop result (duplicates on both sides, int32 and int64 columns,
+    extreme values)."""
+    rng = np.random.default_rng(seed)
+    nR, nS = int(rng.integers(0, 60)), int(rng.integers(0, 200))
+    kR = rng.integers(-6, 6, nR).astype(np.int32)
+    kS = rng.integers(-8, 8, nS).astype(np.int32)
+    colsR = [rng.integers(-2**31, 2**31, nR, dtype=np.int64).astype(np.int32),
+             rng.integers(-2**63, 2**63 - 1, nR, dtype=np.int64), np.arange(nR, dtype=np.int32)]
+    colsS = [rng.integers(-2**63, 2**63 - 1, nS, dtype=np.int64), np.arange(nS, dtype=np.int64) * 3]
+    pairs, outR, outS = oracle.join_wide(kR, colsR, kS, colsS)
+    want = wide_brute_force(kR, colsR, kS, colsS)
+    assert len(pairs) == len(want)
+    assert [((int(p) >> 32), int(p) & 0xFFFFFFFF) for p in pairs] == [(i, j) for i, j, _, _ in want]
+    for c in range(len(colsR)):
+        assert outR[c].dtype == colsR[c].dtype
+        assert [int(v) for v in outR[c]] == [r[2][c] for r in want]
+    for c in range(len(colsS)):
+        assert outS[c].dtype == colsS[c].dtype
+        assert [int(v) for v in outS[c]] == [r[3][c] for r in want]
+
+
+def test_wide_join_row_id_columns_reproduce_the_pairs():
+    """Materializing a column holding each row's own index gives back the pair
+    list (a transposed or shifted gather would not)."""
+    rng = np.random.default_rng(9)
+    kR = rng.integers(0, 300, 2000).astype(np.int64)
+    kS = rng.integers(0, 400, 5000).astype(np.int64)
+    pairs, outR, outS = oracle.join_wide(kR, [np.arange(2000, dtype=np.int64)], kS, [np.arange(5000, dtype=np.int32)])
+    assert np.array_equal(outR[0].astype(np.uint64), pairs >> np.uint64(32))
+    assert np.array_equal(outS[0].astype(np.uint64), pairs & np.uint64(0xFFFFFFFF))
+    assert np.array_equal(kR[outR[0]], kS[outS[0]])

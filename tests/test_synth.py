@@ -128,3 +128,16 @@ def test_generators_identical_on_gpu(gpu):
         a, b = make("cpu"), make(gpu)
         for f in ("build_keys", "build_payload", "probe_keys", "probe_payload"):
             assert torch.equal(getattr(a, f), getattr(b, f).cpu()), f
+
+
+def test_wide_join_shape_and_match_rate():
+    inp = synth.wide_join(seed=3, n_build=5000, n_probe=200000, match_per_mille=300, n_cols=3)
+    assert inp.build_keys.dtype == torch.int32 and len(inp.meta["build_cols"]) == 3
+    assert torch.unique(inp.build_keys).numel() == 5000 and bool((inp.build_keys % 2 == 0).all())
+    hit = (inp.probe_keys % 2 == 0)
+    assert abs(float(hit.float().mean()) - 0.3) < 0.01
+    assert bool(torch.isin(inp.probe_keys[hit], inp.build_keys).all())
+    for c in inp.meta["build_cols"] + inp.meta["probe_cols"]:
+        assert c.dtype == torch.int32
+    w64 = synth.wide_join(seed=3, n_build=100, n_probe=1000, key_dtype=torch.int64, col_dtype=torch.int64)
+    assert w64.probe_keys.dtype == torch.int64 and w64.meta["probe_cols"][2].dtype == torch.int64
