@@ -177,87 +177,201 @@ def kernel_bytes(plan, inp, count):
     return b
 
 
-def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=18.0, reps=5, autotune=False):
-    """4,096 independent unique-key joins of uneven sizes: one hipGraph launch of
-    the batch (per-join plan on the device) against one eiger_join call sequence
-    per join (rule plan, and fixed GLOBAL_HASH). Returns a summary dict."""
+def batch_bytes(nb, npr, lf=0.5):
+    """Device bytes one unique-key int32 join of a batch holds: its four input
+    columns, its output range (one pair per probe row at most) and its table
+    region (16-byte slots, sized as the library sizes them for load factor lf)."""
+    slots = 64
+    while slots < nb / lf + 1.0:
+        slots <<= 1
+    if slots < 2 * nb:
+        slots <<= 1
+    return 8 * nb + 8 * npr + 8 * npr + 16 * slots + 4096
+
+
+def batch_waves(sizes, budget, tune=None):
+    """Split joins (in index order) into the fewest consecutive groups whose
+    batch_bytes sum stays within `budget` bytes."""
+    import paper_2607_04489_amd as eg
+    waves, cur, used = [], [], 0
+    for j, (nb, npr) in enumerate(sizes):
+        lf = (tune or {}).get(eg.batch_bucket(nb), (0.5, 0))[0]
+        b = batch_bytes(nb, npr, lf)
+        if cur and used + b > budget:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(j)
+        used += b
+    if cur:
+        waves.append(cur)
+    return waves
+
+
+def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=False, seed=42):
+    """4,096 independent unique-key int32 joins of uneven sizes (build rows
+    2^U(8,22), probe rows 4-16x, match rate U[0.1,1], half dense / half sparse).
+    The batch does not fit HBM at once (inputs, outputs and tables of all joins
+    are ~380 GB), so the joins are drawn and run in the fewest consecutive
+    waves that fit: per wave one captured hipGraph (per-join plan on the
+    device), timed, then one eiger_join call sequence per join (rule plan, and
+    fixed GLOBAL_HASH) for comparison. Returns a summary dict."""
     import torch
     import paper_2607_04489_amd as eg
     import synth
     from paper_2607_04489_amd import batch as batchmod
     dev = torch.device("cuda:0")
-    inputs = synth.batched_joins(42, n_joins, log2_lo, log2_hi, device=dev)
-    joins = [(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload) for i in inputs]
+    sizes = [synth.batched_join_params(seed, j, log2_lo, log2_hi)[:2] for j in range(n_joins)]
+    max_np = max(n for _, n in sizes)
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.85) - 24 * max_np - (1 << 30)
     tune = None
-    if autotune:
-        tune, _ = batchmod.autotune(joins, log=log)
-    elif os.path.exists(batchmod.TUNE_PATH):
+    if not autotune and os.path.exists(batchmod.TUNE_PATH):
         tune = batchmod.load()
-    b = eg.Batch(joins, tune)
-    b.launch()
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(reps):
-        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        st.record()
+    waves = batch_waves(sizes, budget, tune)
+    graph_ms = rule_ms = fixed_ms = 0.0
+    pairs = direct = flagged = 0
+    agree = True
+    for w, idx in enumerate(waves):
+        inputs = [synth.batched_join(seed, j, log2_lo, log2_hi, device=dev) for j in idx]
+        joins = [(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload) for i in inputs]
+        if autotune and tune is None:
+            tune, _ = batchmod.autotune(joins, log=log)
+        b = eg.Batch(joins, tune)
         b.launch()
-        en.record()
-        en.synchronize()
-        times.append(st.elapsed_time(en))
-    counts, sums, variants, flags = b.results()
-    graph_ms = sum(times) / len(times)
-
-    def per_join(selector):
-        ws = torch.empty(1, dtype=torch.uint8, device=dev)
-        cap = max(i.n_probe for i in inputs)
-        outs = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
-        plans = []
-        for i in inputs:
-            sb, sp = eg.stats(i.build_keys), eg.stats(i.probe_keys)
-            plans.append(eg.join_plan(sb, sp, selector))
-        need = max(eg.join_workspace_size(p, i.build_keys, i.build_payload, i.probe_keys, i.probe_payload)
-                   for p, i in zip(plans, inputs))
-        ws = torch.empty(need, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = [eg.join(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload, p, workspace=ws, outputs=outs)
-               for p, i in zip(plans, inputs)]
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3, res
+        times = []
+        for _ in range(reps):
+            st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st.record()
+            b.launch()
+            en.record()
+            en.synchronize()
+            times.append(st.elapsed_time(en))
+        counts, sums, variants, flags = b.results()
+        graph_ms += sum(times) / len(times)
+        b.destroy()
+        del b
 
-    rule_ms, rres = per_join(eg.SEL_RULE)
-    fixed_ms, fres = per_join(eg.SEL_FIXED_HASH)
-    agree = all((r.count, r.checksum) == (int(c), int(s)) for r, c, s in zip(rres, counts, sums))
-    n_probe = sum(i.n_probe for i in inputs)
-    b.destroy()
-    return {"joins": n_joins, "build_rows": sum(i.n_build for i in inputs), "probe_rows": n_probe,
-            "pairs": int(counts.sum()), "graph_ms": round(graph_ms, 3),
-            "graph_probe_tuples_per_s": n_probe / (graph_ms * 1e-3),
+        def per_join(selector):
+            cap = max(i.n_probe for i in inputs)
+            outs = (torch.empty(cap, dtype=torch.int32, device=dev), torch.empty(cap, dtype=torch.int32, device=dev))
+            plans = [eg.join_plan(eg.stats(i.build_keys), eg.stats(i.probe_keys), selector) for i in inputs]
+            need = max(eg.join_workspace_size(p, i.build_keys, i.build_payload, i.probe_keys, i.probe_payload)
+                       for p, i in zip(plans, inputs))
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = [eg.join(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload, p, workspace=ws,
+                           outputs=outs) for p, i in zip(plans, inputs)]
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3, [(r.count, r.checksum) for r in res]
+
+        t_rule, rres = per_join(eg.SEL_RULE)
+        t_fixed, _ = per_join(eg.SEL_FIXED_HASH)
+        rule_ms += t_rule
+        fixed_ms += t_fixed
+        agree = agree and all(r == (int(c), int(s_)) for r, c, s_ in zip(rres, counts, sums))
+        pairs += int(counts.sum())
+        direct += int((variants == eg.DIRECT).sum())
+        flagged += int((flags != 0).sum())
+        log(f"  wave {w}: {len(idx)} joins, graph {sum(times) / len(times):.2f} ms, per-join rule {t_rule:.1f} ms")
+        del inputs, joins
+        torch.cuda.empty_cache()
+    n_build = sum(n for n, _ in sizes)
+    n_probe = sum(n for _, n in sizes)
+    return {"joins": n_joins, "waves": len(waves), "wave_sizes": [len(x) for x in waves],
+            "build_rows": n_build, "probe_rows": n_probe, "pairs": pairs,
+            "graph_ms": round(graph_ms, 3), "graph_probe_tuples_per_s": n_probe / (graph_ms * 1e-3),
+            "graph_alg_GBps": round((8 * n_build + 8 * n_probe + 8 * pairs) / (graph_ms * 1e-3) / 1e9, 1),
             "per_join_rule_ms": round(rule_ms, 3), "per_join_fixed_hash_ms": round(fixed_ms, 3),
             "speedup_vs_per_join_rule": round(rule_ms / graph_ms, 2),
             "speedup_vs_per_join_fixed_hash": round(fixed_ms / graph_ms, 2),
-            "direct_joins": int((variants == eg.DIRECT).sum()), "flagged": int((flags != 0).sum()),
+            "direct_joins": direct, "flagged": flagged,
             "agrees_with_single_joins": bool(agree), "tuned": tune is not None,
             "workload": (f"{n_joins} unique-key int32 joins, build rows 2^U({log2_lo:g},{log2_hi:g}), probe 4-16x "
-                         f"build, match U[0.1,1], half dense / half sparse keys")}
+                         f"build, match U[0.1,1], half dense / half sparse keys; drawn and run in "
+                         f"{len(waves)} waves that fit HBM")}
+
+
+def host_cores():
+    """Host CPUs this process may run on (the GPU machine grants 16)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
 def cpu_baseline(name):
     """The oracle, untuned, on a 1/32-scale instance of the same workload (same
-    generator and distributions), single-threaded: statistics of both sides and
-    the sort-merge join with canonical pairs."""
+    generator and distributions): statistics of both sides and the sort-merge
+    join with canonical pairs, once on one thread and once with its sorts on
+    every host core (the merge walk and the statistics stay single-threaded,
+    as the oracle is written)."""
     import oracle
     scale = 32 if name in ("sparse_unique64",) or name.startswith("skewed") else 1
     inp = make_workload(name, "cpu", scale=scale)
-    t0 = time.perf_counter()
-    oracle.column_stats(inp.build_keys)
-    oracle.column_stats(inp.probe_keys)
-    _, cnt, _ = oracle.join_sortmerge(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload)
-    dt = time.perf_counter() - t0
-    return {"value": inp.n_probe / dt, "unit": "probe tuples/s", "cores": 1, "kind": "oracle",
+
+    def once(threads):
+        t0 = time.perf_counter()
+        oracle.column_stats(inp.build_keys)
+        oracle.column_stats(inp.probe_keys)
+        _, cnt, _ = oracle.join_sortmerge(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload,
+                                          threads=threads)
+        return time.perf_counter() - t0, cnt
+
+    cores = host_cores()
+    dt1, cnt = once(1)
+    dtn, _ = once(cores)
+    return {"value": inp.n_probe / dtn, "unit": "probe tuples/s", "cores": cores, "kind": "oracle",
+            "single_core_value": inp.n_probe / dt1,
             "sample": (f"1/{scale}-scale instance of the same generator: build {inp.n_build:,}, probe "
-                       f"{inp.n_probe:,} rows ({cnt:,} pairs); stats of both sides + sort-merge join "
-                       f"with canonical pairs; {dt:.1f} s on one host core")}
+                       f"{inp.n_probe:,} rows ({cnt:,} pairs); stats of both sides + sort-merge join with "
+                       f"canonical pairs; {dtn:.1f} s with the sorts on {cores} host threads, {dt1:.1f} s on "
+                       f"one (os.cpu_count() = {os.cpu_count()})")}
+
+
+def ceilings(dev):
+    """Measured HBM ceilings beside the published 8 TB/s: a streaming copy (torch's
+    device-to-device copy of 4 GiB; read + write bytes per second) and random
+    32-byte reads from a 2 GiB table (torch index_select of 32-byte rows at
+    uniformly random row ids, 2^27 reads into a preallocated output), as reads per
+    second and as GB/s of the 128-byte lines they fetch."""
+    import torch
+    n = 1 << 32
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        st, en = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st.record()
+        for _ in range(reps):
+            fn()
+        en.record()
+        en.synchronize()
+        return st.elapsed_time(en) / reps * 1e-3
+
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: dst.copy_(src), 5)
+    del src, dst
+    rows, reads, part = 1 << 26, 1 << 27, 1 << 24
+    table = torch.zeros(rows, 4, dtype=torch.int64, device=dev)
+    g = torch.Generator(device=dev).manual_seed(1)
+    idx = torch.randint(0, rows, (reads,), device=dev, generator=g)
+    out = torch.empty(part, 4, dtype=torch.int64, device=dev)
+
+    def gather():  # in pieces of 2^24 reads (one index_select launch each)
+        for lo in range(0, reads, part):
+            torch.index_select(table, 0, idx[lo:lo + part], out=out)
+
+    t_gather = timed(gather, 3)
+    del table, idx, out
+    torch.cuda.empty_cache()
+    return {"copy_GBps": round(2 * n / t_copy / 1e9, 1),
+            "copy_frac_of_peak": round(2 * n / t_copy / 1e9 / HBM_PEAK_GBS, 3),
+            "random_32B_reads_per_s": round(reads / t_gather / 1e9, 2) * 1e9,
+            "random_read_line_GBps": round(reads * 128 / t_gather / 1e9, 1),
+            "what": "copy: torch device-to-device copy of 4 GiB; random: index_select of 2^27 random "
+                    "32-byte rows of a 2 GiB table in 8 launches (plus 8-byte ids read and 32 bytes written "
+                    "per read)"}
 
 
 def main():
@@ -273,6 +387,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the fixed-hash comparison run")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--calibrate-gather", action="store_true",
+                    help="only run random 32-byte-row gathers from a 2 GiB table (counter check) and exit")
+    ap.add_argument("--no-ceilings", action="store_true", help="skip the copy / random-read ceilings")
     ap.add_argument("--summarize-profile", default="", metavar="DIR",
                     help="summarize rocprofv3 CSV output under DIR for --kernel and exit (no GPU)")
     ap.add_argument("--kernel", default="hash_probe")
@@ -307,6 +424,20 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
+    if args.calibrate_gather:
+        # 2^24 random 32-byte rows of a 2 GiB table: 512 MiB of row bytes, 128 MiB
+        # of ids read, 512 MiB written; FETCH_SIZE shows the lines the reads fetch
+        rows, reads = 1 << 26, 1 << 24
+        table = torch.zeros(rows, 4, dtype=torch.int64, device="cuda:0")
+        idx = torch.randint(0, rows, (reads,), device="cuda:0",
+                            generator=torch.Generator(device="cuda:0").manual_seed(1))
+        out = torch.empty(reads, 4, dtype=torch.int64, device="cuda:0")
+        for _ in range(3):
+            torch.index_select(table, 0, idx, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_gather_reads": reads, "row_bytes": 32, "table_bytes": rows * 32,
+                          "gathers": 3}), flush=True)
         return
 
     if not eg.available():
@@ -458,6 +589,9 @@ def main():
         out["vs_rule_planner"] = rule_cmp
     if batched:
         out["batched"] = batched
+    if not args.no_ceilings:
+        log("measuring the copy and random-read ceilings")
+        out["ceilings"] = ceilings(dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -111,6 +111,12 @@ def lib():
         L.eiger_join.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                  ctypes.POINTER(i64), ctypes.POINTER(i64), vp, sz, vp]
         L.eiger_join.restype = ctypes.c_int
+        L.eiger_join_wide_workspace_size.argtypes = [ctypes.POINTER(PlanT), i32, Column, vp, i32, Column, vp, i32,
+                                                     ctypes.POINTER(sz)]
+        L.eiger_join_wide_workspace_size.restype = ctypes.c_int
+        L.eiger_join_wide.argtypes = [Column, vp, i32, Column, vp, i32, ctypes.POINTER(PlanT), i32, vp, vp, vp, vp,
+                                      i64, ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
+        L.eiger_join_wide.restype = ctypes.c_int
         L.eiger_join_noalloc.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.eiger_join_noalloc.restype = ctypes.c_int
@@ -292,6 +298,75 @@ def join(bk, bp, pk, pp, plan: PlanT, capacity: Optional[int] = None, stream=Non
         rc = run(ob, op, capacity)
     _check(rc, cnt.value)
     return JoinResult(ob[: cnt.value], op[: cnt.value], cnt.value, cs.value)
+
+
+MAT_GFUR, MAT_GFTR, MAT_AUTO = 0, 1, 2
+MAT_NAMES = {MAT_GFUR: "gfur", MAT_GFTR: "gftr"}
+
+
+@dataclass
+class WideResult:
+    build_rowid: object   # torch.int32 tensors holding uint32 row ids, length count
+    probe_rowid: object
+    build_cols: list      # materialized payload columns, each in its input column's dtype
+    probe_cols: list
+    count: int
+    materialized: int     # MAT_GFUR or MAT_GFTR
+
+
+def _col_array(cols):
+    arr = (Column * max(len(cols), 1))()
+    for i, t in enumerate(cols):
+        arr[i] = column(t)
+    return arr
+
+
+def join_wide(bk, bcols, pk, pcols, plan: PlanT, materialize: int = MAT_AUTO, capacity: Optional[int] = None,
+              stream=None, workspace=None, count_only: bool = False) -> WideResult:
+    """eiger_join_wide: the join with every payload column of both sides
+    materialized (GFUR, GFTR or AUTO). Outputs are allocated here (capacity
+    defaults to the plan's prediction with headroom, at least the probe rows);
+    a result that does not fit is run again once at its exact size."""
+    import torch
+    ca, cb = _col_array(bcols), _col_array(pcols)
+    kb, kp = column(bk), column(pk)
+    need = ctypes.c_size_t()
+    _check(lib().eiger_join_wide_workspace_size(ctypes.byref(plan), int(materialize), kb, ca, len(bcols), kp, cb,
+                                                len(pcols), ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value, pk.device)
+    cnt, used = ctypes.c_int64(), ctypes.c_int32()
+
+    def run(cap):
+        if cap == 0:
+            outs = (None, None, [], [])
+            ptr_b = ptr_p = None
+        else:
+            outs = (torch.empty(cap, dtype=torch.int32, device=pk.device),
+                    torch.empty(cap, dtype=torch.int32, device=pk.device),
+                    [torch.empty(cap, dtype=t.dtype, device=pk.device) for t in bcols],
+                    [torch.empty(cap, dtype=t.dtype, device=pk.device) for t in pcols])
+            ptr_b = (ctypes.c_void_p * max(len(bcols), 1))(*[t.data_ptr() for t in outs[2]])
+            ptr_p = (ctypes.c_void_p * max(len(pcols), 1))(*[t.data_ptr() for t in outs[3]])
+        rc = lib().eiger_join_wide(kb, ca, len(bcols), kp, cb, len(pcols), ctypes.byref(plan), int(materialize),
+                                   ctypes.c_void_p(outs[0].data_ptr()) if cap else None,
+                                   ctypes.c_void_p(outs[1].data_ptr()) if cap else None,
+                                   ptr_b, ptr_p, cap, ctypes.byref(cnt), ctypes.byref(used),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+        return rc, outs
+
+    if count_only:
+        rc, _ = run(0)
+        _check(rc, cnt.value)
+        return WideResult(None, None, [], [], cnt.value, used.value)
+    if capacity is None:
+        capacity = max(int(plan.predicted_out * 1.25) + 1024, pk.numel())
+    rc, outs = run(capacity)
+    if rc == EIGER_ERR_CAPACITY:
+        del outs
+        rc, outs = run(cnt.value)
+    _check(rc, cnt.value)
+    n = cnt.value
+    return WideResult(outs[0][:n], outs[1][:n], [t[:n] for t in outs[2]], [t[:n] for t in outs[3]], n, used.value)
 
 
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
@@ -488,6 +563,18 @@ class Batch:
     def pairs(self, j, count):
         lo = self.offsets[j]
         return self.out_b[lo:lo + count], self.out_p[lo:lo + count]
+
+    def resolve_flagged(self, flags, selector: int = SEL_RULE, stream=None) -> dict:
+        """Joins the batch flagged (repeated build keys: the graph's first-match
+        probes do not hold for them) run again one by one through eiger_join with
+        the `selector` plan, which handles duplicates. Returns {join index:
+        JoinResult}; the batch's own output ranges of those joins are not used."""
+        out = {}
+        for j in (int(x) for x in (flags != 0).nonzero()[0]):
+            bk, bp, pk, pp = self.joins[j]
+            plan = join_plan(stats(bk, stream), stats(pk, stream), selector)
+            out[j] = join(bk, bp, pk, pp, plan, stream=stream)
+        return out
 
     def destroy(self):
         if self.handle:

@@ -98,3 +98,66 @@ def test_batch_rejects_bad_descriptors(gpu):
     with pytest.raises(eg.EigerError):
         eg.Batch([(inp[0].build_keys, inp[0].build_payload, inp[0].probe_keys.to(torch.int64),
                    inp[0].probe_payload)])
+
+
+def test_batch_flagged_joins_resolve_through_eiger_join(gpu):
+    """Joins with repeated build keys are flagged by the graph and joined again
+    through eiger_join; their results equal the oracle's."""
+    inputs = small_batch(gpu, n=12, seed=8)
+    for j in (1, 4):
+        bk = inputs[j].build_keys.clone()
+        bk[1::3] = bk[0]  # many copies of one key
+        inputs[j] = synth.JoinInput("dups", bk, inputs[j].build_payload, inputs[j].probe_keys,
+                                    inputs[j].probe_payload)
+    b = eg.Batch([as_tuple(i) for i in inputs])
+    b.launch()
+    _, _, _, flags = check_batch(b, inputs, flags_expected={1, 4})
+    fixed = b.resolve_flagged(flags)
+    assert sorted(fixed) == [1, 4]
+    for j, res in fixed.items():
+        pairs, cnt, cs = oracle.join_sortmerge(*as_tuple(inputs[j]))
+        assert (res.count, res.checksum) == (cnt, cs)
+        got = oracle.canonical_pairs(res.build_rowid.cpu().numpy().view(np.uint32),
+                                     res.probe_rowid.cpu().numpy().view(np.uint32))
+        assert np.array_equal(got, pairs)
+
+
+def test_batch_spec_shape_in_waves(gpu):
+    """Joins of the batched workload's full size range (build rows 2^U(8,22),
+    probe rows 4-16x) run in two graph waves; 64 joins -- the 8 largest and 56
+    more drawn with a seed -- are compared pair for pair with the oracle, and
+    every join's count and checksum with the single-join path."""
+    from joincheck import host_threads
+    n, seed = 192, 11
+    sizes = [synth.batched_join_params(seed, j, 8.0, 22.0)[:2] for j in range(n)]
+    assert max(nb for nb, _ in sizes) > (1 << 21)
+    largest = sorted(range(n), key=lambda j: -sizes[j][1])[:8]
+    rng = np.random.default_rng(seed)
+    rest = [j for j in range(n) if j not in largest]
+    sample = set(largest) | set(int(j) for j in rng.choice(rest, 56, replace=False))
+    checked = 0
+    for wave in (range(0, n // 2), range(n // 2, n)):
+        inputs = {j: synth.batched_join(seed, j, 8.0, 22.0, device=gpu) for j in wave}
+        order = list(wave)
+        b = eg.Batch([as_tuple(inputs[j]) for j in order])
+        b.launch()
+        counts, sums, _, flags = b.results()
+        assert not flags.any()
+        for t, j in enumerate(order):
+            inp = inputs[j]
+            if j in sample:
+                print(f"[batch-spec] join {j}: {inp.n_build} x {inp.n_probe}", flush=True)
+                pairs, cnt, cs = oracle.join_sortmerge(*as_tuple(inp), threads=host_threads())
+                assert (counts[t], sums[t]) == (cnt, cs), j
+                ob, op = b.pairs(t, cnt)
+                got = oracle.canonical_pairs(ob.cpu().numpy().view(np.uint32), op.cpu().numpy().view(np.uint32))
+                assert np.array_equal(got, pairs), j
+                checked += 1
+            else:
+                r = eg.join(*as_tuple(inp), eg.join_plan(eg.stats(inp.build_keys), eg.stats(inp.probe_keys)),
+                            count_only=True)
+                assert (r.count, r.checksum) == (counts[t], sums[t]), j
+        b.destroy()
+        del inputs
+        torch.cuda.empty_cache()
+    assert checked == 64
