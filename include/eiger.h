@@ -194,6 +194,55 @@ int eiger_join(eiger_column build_keys, eiger_column build_payload, eiger_column
                uint32_t *out_probe_rowid, int64_t out_capacity, int64_t *out_count,
                int64_t *out_checksum, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- wide joins (payload columns materialized) ------------------------------
+ * The "wide join" of Section 5.2.1: every result pair also carries the payload
+ * columns of both relations. Two ways to produce them (Section 3.2):
+ *  EIGER_MAT_GFUR  gather from the untransformed relations: join the keys with
+ *                  any variant, then gather each payload column from the
+ *                  caller's columns by row id (random reads).
+ *  EIGER_MAT_GFTR  gather from the transformed relations (RADIX plans only):
+ *                  the payload columns are carried through the partitioning
+ *                  passes with the keys, and each result block gathers its
+ *                  payloads from one partition's contiguous range.
+ *  EIGER_MAT_AUTO  GFTR for RADIX plans whose estimated match ratio
+ *                  (predicted_out / probe rows) is at least 0.25, else GFUR
+ *                  (Section 5.2.3: GFUR wins at low match ratios).
+ * With no payload column on either side the two coincide (GFUR is reported). */
+typedef enum { EIGER_MAT_GFUR = 0, EIGER_MAT_GFTR = 1, EIGER_MAT_AUTO = 2 } eiger_materialize;
+
+/* Workspace bytes of eiger_join_wide for these columns (data not read). */
+int eiger_join_wide_workspace_size(const eiger_plan_t *plan, int32_t materialize, eiger_column build_keys,
+                                   const eiger_column *build_cols, int32_t n_build_cols,
+                                   eiger_column probe_keys, const eiger_column *probe_cols,
+                                   int32_t n_probe_cols, size_t *bytes);
+
+/*
+ * Inner equi-join of R and S with materialized payloads. Result row t is a
+ * pair (i, j) with build_keys[i] == probe_keys[j]:
+ *   out_build_rowid[t] = i, out_probe_rowid[t] = j,
+ *   out_build_cols[c][t] = build_cols[c][i]   (c < n_build_cols),
+ *   out_probe_cols[c][t] = probe_cols[c][j]   (c < n_probe_cols),
+ * rows in no particular order, each output column in its input column's dtype.
+ *  build_cols, probe_cols  HOST arrays of 0..4 DEVICE columns (int32 or int64,
+ *                 as many rows as their side's keys)
+ *  plan           from eiger_join_plan; its variant joins the keys
+ *  materialize    eiger_materialize; *out_materialized (HOST, may be NULL)
+ *                 receives the strategy used
+ *  out_*          DEVICE arrays of out_capacity entries (out_*_cols: HOST arrays
+ *                 of DEVICE pointers); out_capacity == 0 with NULL row-id
+ *                 outputs counts only
+ *  out_count      HOST: number of result rows
+ * EIGER_ERR_CAPACITY when the result exceeds out_capacity (*out_count set,
+ * outputs hold an unspecified subset); EIGER_ERR_UNSUPPORTED for GFTR with a
+ * plan other than RADIX. Synchronizes `stream`.
+ */
+int eiger_join_wide(eiger_column build_keys, const eiger_column *build_cols, int32_t n_build_cols,
+                    eiger_column probe_keys, const eiger_column *probe_cols, int32_t n_probe_cols,
+                    const eiger_plan_t *plan, int32_t materialize, uint32_t *out_build_rowid,
+                    uint32_t *out_probe_rowid, void *const *out_build_cols, void *const *out_probe_cols,
+                    int64_t out_capacity, int64_t *out_count, int32_t *out_materialized, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* Bytes of the fixed device scratch array behind eiger_join_noalloc (64 MiB). */
 #define EIGER_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 
@@ -357,6 +406,17 @@ int eiger_profile_enable(int on);
 /* Copies up to max_entries rows into HOST `out`, sets *n_out to the number of
  * distinct kernels seen. Resolves pending events (synchronizes them). */
 int eiger_profile_read(eiger_kernel_time_t *out, int max_entries, int *n_out);
+
+/* Bandwidth ceilings for measurement reports (not part of the join path),
+ * timed with HIP events on `stream`; *ms (HOST) receives the kernel time.
+ *  kind 0  copy n_bytes (a multiple of 16) from DEVICE a to DEVICE b with
+ *          16-byte loads and stores (read + write bytes = 2 n_bytes)
+ *  kind 1  `reads` random 32-byte reads (8 in flight per thread) from the
+ *          DEVICE table a of n_bytes (the largest power-of-two number of
+ *          32-byte slots that fits is used); DEVICE b receives one 4-byte word
+ *          per 64 reads
+ * Synchronizes `stream`. */
+int eiger_calibrate(int32_t kind, void *a, void *b, int64_t n_bytes, int64_t reads, double *ms, void *stream);
 
 #ifdef __cplusplus
 }

@@ -117,6 +117,8 @@ def lib():
         L.eiger_join_wide.argtypes = [Column, vp, i32, Column, vp, i32, ctypes.POINTER(PlanT), i32, vp, vp, vp, vp,
                                       i64, ctypes.POINTER(i64), ctypes.POINTER(i32), vp, sz, vp]
         L.eiger_join_wide.restype = ctypes.c_int
+        L.eiger_calibrate.argtypes = [i32, vp, vp, i64, i64, ctypes.POINTER(ctypes.c_double), vp]
+        L.eiger_calibrate.restype = ctypes.c_int
         L.eiger_join_noalloc.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.eiger_join_noalloc.restype = ctypes.c_int

@@ -191,6 +191,17 @@ int run_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   }
 }
 
+}  // namespace
+
+int run_join_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) { return run_variant(a, ws, ctr); }
+
+int check_join_inputs_public(const eiger_column &bk, const eiger_column &bp, const eiger_column &pk,
+                             const eiger_column &pp, const eiger_plan_t *plan) {
+  return check_join_inputs(bk, bp, pk, pp, plan);
+}
+
+namespace {
+
 // ------------------------------------------------------------------ planning
 
 constexpr double kHashTableBudget = 4.0 * 1024 * 1024 * 1024;  // bytes a GLOBAL_HASH table may take

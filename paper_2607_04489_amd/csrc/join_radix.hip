@@ -567,7 +567,7 @@ __device__ __forceinline__ void join_chunk_grouped(const int32_t *__restrict__ r
     uint32_t i = tab.home(rk[j]);
     while (static_cast<uint32_t>(W[i] >> 32) != key || (W[i] & 0xFFFFu) == 0) i = tab.next(i);
     const uint32_t pos = static_cast<uint32_t>((atomicAdd(&W[i], 1ull << 16) >> 16) & 0xFFFFu);
-    rid[pos] = rr[j];
+    rid[pos] = rr ? rr[j] : j;  // no row-id array: the row's position (wide joins)
     ps[pos] = static_cast<uint64_t>(sext(rp[j]));
   }
   __syncthreads();
@@ -611,7 +611,7 @@ __device__ __forceinline__ void join_chunk_multiset(const K *__restrict__ rk, co
     const K key = rk[j];
     uint32_t i = tab.home(key);
     for (;;) {
-      if (atomicCAS(&tr[i], kEmpty, rr[j]) == kEmpty) {
+      if (atomicCAS(&tr[i], kEmpty, rr ? rr[j] : j) == kEmpty) {
         tk[i] = key;
         tp[i] = rp[j];
         break;
@@ -852,6 +852,239 @@ int radix_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   return EIGER_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Wide joins, GFTR materialization (Section 3.2: the payload columns go
+// through the same partitioning as the keys): the scatter carries up to
+// kMaxWords 32-bit payload words per tuple along with the key and row id, and
+// the join emits positions in the partitioned arrays, from which the payload
+// words are later gathered partition by partition.
+
+// Up to kMaxWords 32-bit word lanes. Lane w of row i is src[w][i * src_stride[w]]
+// (an 8-byte column is two lanes, its low and high words, with stride 2); the
+// scatter writes it to dst[w][position] (stride 1).
+struct Lanes {
+  const uint32_t *src[kMaxWords];
+  uint32_t src_stride[kMaxWords];
+  uint32_t *dst[kMaxWords];
+  int n;
+};
+
+// k_part_scatter's tile sort, moving key, row id and the word lanes.
+template <typename K, bool kRows>
+__global__ void __launch_bounds__(kPNT)
+    k_part_scatter_carry(const K *__restrict__ keys, const uint32_t *__restrict__ rows, Lanes lanes,
+                         const uint32_t *__restrict__ seg_off, const uint32_t *__restrict__ cpre, uint32_t nseg,
+                         int shift, int bits, const uint32_t *__restrict__ C, K *__restrict__ okeys,
+                         uint32_t *__restrict__ orows) {
+  __shared__ K lk[kPTile];
+  __shared__ uint32_t lr[kPTile];
+  __shared__ uint32_t lw[kMaxWords][kPTile];
+  __shared__ uint16_t lb[kPTile];
+  __shared__ uint32_t hist[kMaxB], gcur[kMaxB], gdst[kMaxB], loff[kMaxB];
+  __shared__ uint32_t scan_tmp[kPNT / 64 + 1];
+  const uint32_t c = blockIdx.x;
+  if (c >= cpre[nseg]) return;
+  const uint32_t B = 1u << bits;
+  const uint32_t s = find_segment(cpre, nseg, c);
+  const uint32_t lc = c - cpre[s], nch = cpre[s + 1] - cpre[s];
+  const uint32_t lo = seg_off[s] + lc * kChunk;
+  const uint32_t hi = min(seg_off[s + 1], lo + kChunk);
+  for (uint32_t b = threadIdx.x; b < B; b += kPNT) {
+    hist[b] = 0;
+    gcur[b] = C[uint64_t(cpre[s]) * B + uint64_t(b) * nch + lc];
+  }
+  __syncthreads();
+  for (uint32_t t0 = lo; t0 < hi; t0 += kPTile) {
+    const uint32_t t1 = min(hi, t0 + kPTile);
+    K key[kPIPT];
+    uint32_t row[kPIPT], bk[kPIPT], rk[kPIPT];
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      const uint32_t i = t0 + k * kPNT + threadIdx.x;
+      if (i < t1) {
+        key[k] = keys[i];
+        row[k] = kRows ? rows[i] : i;
+        bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
+        rk[k] = atomicAdd(&hist[bk[k]], 1u);
+      }
+    }
+    __syncthreads();
+    uint32_t v[kBPT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kBPT; ++j) {
+      const uint32_t b = threadIdx.x * kBPT + j;
+      v[j] = b < B ? hist[b] : 0u;
+      sum += v[j];
+    }
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan<kPNT>(sum, scan_tmp, &total);
+#pragma unroll
+    for (int j = 0; j < kBPT; ++j) {
+      const uint32_t b = threadIdx.x * kBPT + j;
+      if (b < B) {
+        loff[b] = ex;
+        gdst[b] = gcur[b] - ex;
+        gcur[b] += v[j];
+        hist[b] = 0;
+        ex += v[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPIPT; ++k) {
+      const uint32_t i = t0 + k * kPNT + threadIdx.x;
+      if (i < t1) {
+        const uint32_t pos = loff[bk[k]] + rk[k];
+        lk[pos] = key[k];
+        lr[pos] = row[k];
+        lb[pos] = static_cast<uint16_t>(bk[k]);
+        for (int w = 0; w < lanes.n; ++w) lw[w][pos] = lanes.src[w][uint64_t(i) * lanes.src_stride[w]];
+      }
+    }
+    __syncthreads();
+    const uint32_t n = t1 - t0;
+    for (uint32_t e = threadIdx.x; e < n; e += kPNT) {
+      const uint32_t dst = gdst[lb[e]] + e;
+      okeys[dst] = lk[e];
+      orows[dst] = lr[e];
+      for (int w = 0; w < lanes.n; ++w) lanes.dst[w][dst] = lw[w][e];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename K, bool kRows>
+int part_pass_carry(const K *ik, const uint32_t *ir, const Lanes &lanes, K *ok, uint32_t *orow, uint64_t n,
+                    const uint32_t *seg_off, const uint32_t *cpre, uint32_t nseg, int shift, int bits,
+                    uint32_t *C, uint64_t *tmp, uint64_t *total, uint32_t *part_off, hipStream_t s) {
+  const uint64_t ub = ub_chunks(n, nseg);
+  const uint64_t nC = ub << bits;
+  int rc;
+  if ((rc = fill_u32(C, nC, 0, s))) return rc;
+  EIGER_LAUNCH("radix_hist", k_part_hist<K>, dim3(unsigned(ub)), dim3(kPNT), 0, s, ik, seg_off, cpre, nseg, shift,
+               bits, C);
+  if ((rc = exclusive_scan_u32(C, C, nC, tmp, total, s))) return rc;
+  EIGER_LAUNCH("radix_scatter", (k_part_scatter_carry<K, kRows>), dim3(unsigned(ub)), dim3(kPNT), 0, s, ik, ir,
+               lanes, seg_off, cpre, nseg, shift, bits, C, ok, orow);
+  const uint64_t nq = (uint64_t(nseg) << bits) + 1;
+  EIGER_LAUNCH("radix_offsets", k_part_offsets, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, s, seg_off, cpre,
+               nseg, bits, C, part_off, static_cast<uint32_t>(n));
+  return EIGER_OK;
+}
+
+// One side of a wide radix join: keys, row ids and nw word lanes per pass.
+template <typename K>
+struct WideSide {
+  K *k[2];
+  uint32_t *r[2];
+  uint32_t *w[2][kMaxWords];
+  uint32_t *seg1, *cpre1, *off1, *cpre2, *off;
+};
+
+template <typename K>
+WideSide<K> wide_side_layout(Workspace &ws, uint64_t n, int nw, const PassPlan &pp) {
+  WideSide<K> S{};
+  const uint64_t m = n ? n : 1;
+  for (int q = 0; q < pp.passes; ++q) {
+    S.k[q] = ws.take<K>(m);
+    S.r[q] = ws.take<uint32_t>(m);
+    for (int w = 0; w < nw; ++w) S.w[q][w] = ws.take<uint32_t>(m);
+  }
+  S.seg1 = ws.take<uint32_t>(2);
+  S.cpre1 = ws.take<uint32_t>(2);
+  S.off1 = ws.take<uint32_t>((uint64_t(1) << pp.bits[0]) + 1);
+  S.cpre2 = ws.take<uint32_t>((uint64_t(1) << pp.bits[0]) + 1);
+  S.off = pp.passes == 2 ? ws.take<uint32_t>((uint64_t(1) << (pp.bits[0] + pp.bits[1])) + 1) : S.off1;
+  return S;
+}
+
+// Partition a side carrying its word lanes (src); the final pass's arrays are
+// S.k[last], S.r[last], S.w[last][*].
+template <typename K>
+int partition_side_carry(const K *keys, const Lanes &src, uint64_t n, WideSide<K> &S, const PassPlan &pp,
+                         uint32_t *C, uint64_t *tmp, uint64_t *total, hipStream_t s) {
+  EIGER_LAUNCH("radix_seg", k_single_segment, dim3(1), dim3(64), 0, s, S.seg1, S.cpre1, static_cast<uint32_t>(n));
+  Lanes l1 = src;
+  for (int w = 0; w < src.n; ++w) l1.dst[w] = S.w[0][w];
+  int rc;
+  const int b1 = pp.bits[0];
+  if ((rc = part_pass_carry<K, false>(keys, nullptr, l1, S.k[0], S.r[0], n, S.seg1, S.cpre1, 1, 64 - b1, b1, C, tmp,
+                                      total, S.off1, s)))
+    return rc;
+  if (pp.passes == 1) return EIGER_OK;
+  const uint32_t nseg = 1u << b1;
+  EIGER_LAUNCH("radix_chunks", k_chunk_counts, dim3((nseg + 1 + 255) / 256), dim3(256), 0, s, S.off1, nseg, S.cpre2);
+  if ((rc = exclusive_scan_u32(S.cpre2, S.cpre2, nseg + 1, tmp, total, s))) return rc;
+  Lanes l2{};
+  l2.n = src.n;
+  for (int w = 0; w < src.n; ++w) {
+    l2.src[w] = S.w[0][w];
+    l2.src_stride[w] = 1;
+    l2.dst[w] = S.w[1][w];
+  }
+  const int b2 = pp.bits[1];
+  return part_pass_carry<K, true>(S.k[0], S.r[0], l2, S.k[1], S.r[1], n, S.off1, S.cpre2, nseg, 64 - b1 - b2, b2, C,
+                                  tmp, total, S.off, s);
+}
+
+template <typename K>
+int radix_wide_impl(const JoinArgs &a, const WordCols &colsR, const WordCols &colsS, Workspace &ws,
+                    JoinCounters **ctr, WideSource *outR, WideSource *outS) {
+  const PassPlan pp = split_bits(a.plan.radix_bits, a.plan.radix_passes);
+  const int bits = pp.bits[0] + pp.bits[1];
+  const uint32_t F = 1u << bits;
+  float lf = a.plan.load_factor;
+  if (!(lf > 0.f) || lf > 0.9f) lf = 0.5f;
+  const RadixLimits lim = radix_limits(a.kdt, a.kdt, lf);
+  JoinCounters *c = ws.take<JoinCounters>(1);
+  WideSide<K> R = wide_side_layout<K>(ws, a.nR, colsR.n, pp);
+  WideSide<K> S = wide_side_layout<K>(ws, a.nS, colsS.n, pp);
+  const uint64_t nC = std::max(counters_len(a.nR, pp), counters_len(a.nS, pp));
+  uint32_t *C = ws.take<uint32_t>(nC);
+  uint64_t *tmp = ws.take<uint64_t>(scan_tmp_elems(std::max<uint64_t>(nC, F + 1)));
+  uint64_t *total = ws.take<uint64_t>(1);
+  uint32_t *items = ws.take<uint32_t>(F + 1);
+  uint32_t *item_part = ws.take<uint32_t>(uint64_t(F) + (a.nS + kJTile - 1) / kJTile + 1);
+  *ctr = c;
+  const int last = pp.passes - 1;
+  outR->rows = R.r[last];
+  outS->rows = S.r[last];
+  for (int w = 0; w < kMaxWords; ++w) {
+    outR->words[w] = w < colsR.n ? R.w[last][w] : nullptr;
+    outS->words[w] = w < colsS.n ? S.w[last][w] : nullptr;
+  }
+  if (!ws.base) return EIGER_OK;
+  hipStream_t s = a.s;
+  int rc;
+  if ((rc = fill_u64(reinterpret_cast<uint64_t *>(c), 4, 0, s))) return rc;
+  if (a.nR == 0 || a.nS == 0) return EIGER_OK;
+  Lanes lr{}, ls{};
+  lr.n = colsR.n;
+  ls.n = colsS.n;
+  for (int w = 0; w < colsR.n; ++w) {
+    lr.src[w] = colsR.src[w];
+    lr.src_stride[w] = colsR.stride[w];
+  }
+  for (int w = 0; w < colsS.n; ++w) {
+    ls.src[w] = colsS.src[w];
+    ls.src_stride[w] = colsS.stride[w];
+  }
+  if ((rc = partition_side_carry<K>(static_cast<const K *>(a.bk), lr, a.nR, R, pp, C, tmp, total, s))) return rc;
+  if ((rc = partition_side_carry<K>(static_cast<const K *>(a.pk), ls, a.nS, S, pp, C, tmp, total, s))) return rc;
+  EIGER_LAUNCH("radix_items", k_items, dim3((F + 1 + 255) / 256), dim3(256), 0, s, R.off, S.off, F, items);
+  if ((rc = exclusive_scan_u32(items, items, F + 1, tmp, total, s))) return rc;
+  EIGER_LAUNCH("radix_items", k_item_part, dim3((F + 255) / 256), dim3(256), 0, s, items, F, item_part);
+  // positions, not row ids: no row-id arrays go in, and the keys stand in for
+  // the payloads (the wide join reports no payload aggregate)
+  EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
+  const unsigned grid = static_cast<unsigned>(device_cu_count()) * 2;
+  const K *rk = R.k[last], *sk = S.k[last];
+  EIGER_LAUNCH("radix_join", (k_radix_join<K, K, K>), dim3(grid), dim3(kJNT), 0, s, rk, rk,
+               static_cast<const uint32_t *>(nullptr), R.off, sk, sk, static_cast<const uint32_t *>(nullptr), S.off,
+               items, item_part, F, lim.max_build, lf, o);
+  return EIGER_OK;
+}
+
 }  // namespace
 
 RadixLimits radix_limits(int32_t kdt, int32_t bpdt, float lf) {
@@ -882,6 +1115,12 @@ int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   if (k64 && b64 && !p64) EIGER_DISPATCH(int64_t, int64_t, int32_t);
   EIGER_DISPATCH(int64_t, int64_t, int64_t);
 #undef EIGER_DISPATCH
+}
+
+int run_radix_wide(const JoinArgs &a, const WordCols &colsR, const WordCols &colsS, Workspace &ws, JoinCounters **ctr,
+                   WideSource *outR, WideSource *outS) {
+  if (a.kdt == EIGER_INT64) return radix_wide_impl<int64_t>(a, colsR, colsS, ws, ctr, outR, outS);
+  return radix_wide_impl<int32_t>(a, colsR, colsS, ws, ctr, outR, outS);
 }
 
 }  // namespace eiger

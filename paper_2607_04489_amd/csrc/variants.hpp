@@ -33,6 +33,28 @@ int run_global_hash(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_radix_cache(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 
+// Wide joins: payload columns as 32-bit word lanes (an 8-byte column is two
+// lanes, low word then high word, each with stride 2).
+constexpr int kMaxWords = 8;
+struct WordCols {
+  const uint32_t *src[kMaxWords];
+  uint32_t stride[kMaxWords];
+  int n;
+};
+// Where a wide join's materialization reads from: the partitioned row ids and
+// word arrays of one side (GFTR), filled in by run_radix_wide.
+struct WideSource {
+  const uint32_t *rows;
+  const uint32_t *words[kMaxWords];
+};
+// RADIX join of the keys in a (payloads ignored) carrying the word lanes of
+// both sides through the partitioning (GFTR); the output pairs are positions
+// in the final partitioned arrays, described by *outR / *outS.
+int run_radix_wide(const JoinArgs &a, const WordCols &colsR, const WordCols &colsS, Workspace &ws, JoinCounters **ctr,
+                   WideSource *outR, WideSource *outS);
+// Dispatch of eiger_join's variants (abi.hip).
+int run_join_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+
 // Largest key range the DIRECT variant accepts (its offset table is 4 B per key value).
 constexpr uint64_t kDirectMaxRange = uint64_t(1) << 30;
 
