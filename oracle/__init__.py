@@ -9,6 +9,7 @@ Contents (each function cites the passage of the paper it follows):
   * join_totals     -- count and checksum from per-key aggregates of R
   * probe_matches   -- matching build rows of sampled probe rows
   * join_wide       -- the join result with both sides' payload columns materialized
+  * group_by        -- groups of a key column with a count and per-column sums
   * column_stats    -- count, min, max, HLL registers and distinct estimate
   * fmix64          -- the 64-bit hash used by the sketch
 The C part lives in ``eiger_oracle.c`` and is compiled with gcc on first use.
@@ -243,6 +244,27 @@ def join_wide(kR, colsR, kS, colsS, threads: int = 1):
     i = (pairs >> np.uint64(32)).astype(np.int64)
     j = (pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)
     return pairs, [_host(c)[i] for c in colsR], [_host(c)[j] for c in colsS]
+
+
+def group_by(keys, vals):
+    """Group-by with a count and a sum per value column (Section 3.3 group-by
+    operators; Section 4.1 / 5.3: the number of groups decides between the
+    hash-based and the partition-based algorithm, both of which produce this
+    result). Plain definition: the groups are the distinct key values; group k
+    has count = #{i : keys[i] == k} and, for value column c,
+    sum_c = sum over those rows of vals[c][i] (sign-extended, mod 2^64, as
+    int64). Returns (group keys ascending as int64, counts int64, [sums int64])."""
+    k = _as_i64(keys)
+    if k.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), [np.zeros(0, np.int64) for _ in vals]
+    uniq, inv = np.unique(k, return_inverse=True)
+    counts = np.bincount(inv, minlength=uniq.size).astype(np.int64)
+    sums = []
+    for v in vals:
+        acc = np.zeros(uniq.size, dtype=np.uint64)
+        np.add.at(acc, inv, _as_i64(v).view(np.uint64))
+        sums.append(acc.view(np.int64))
+    return uniq, counts, sums
 
 
 def canonical_pairs(build_rows, probe_rows) -> np.ndarray:

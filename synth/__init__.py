@@ -198,6 +198,29 @@ def wide_join(seed: int = 42, n_build: int = 1 << 16, n_probe: int = 1 << 28, ma
                      meta={"build_cols": bcols, "probe_cols": pcols, "match_per_mille": match_per_mille})
 
 
+def groupby_input(seed: int = 42, n: int = 1 << 28, groups: int = 1 << 10, key_dtype=torch.int32,
+                  n_vals: int = 2, val_dtype=torch.int32, device="cpu"):
+    """Group-by input (the paper's group-by microbenchmarks, Section 5.3: a key
+    column with g groups and two aggregated columns): each row's key is one of
+    `groups` distinct values, drawn uniformly; the distinct values are spread
+    over the key type's positive range (a keyed bijection of [0, groups) for
+    int32, SplitMix64 outputs for int64). Value columns uniform over the value
+    type's full range. Returns (keys, [value columns])."""
+    dev = torch.device(device)
+    idx = torch.arange(n, dtype=torch.int64, device=dev)
+    gid = uniform_below(rand64(seed, 1, idx), max(groups, 1))
+    if key_dtype == torch.int32:
+        bits = max(1, min(31, (max(groups, 2) - 1).bit_length()))
+        keys = (bij_bits(gid, bits, seed) << (31 - bits)).to(torch.int32)
+    else:
+        keys = mix64(gid + _stream_base(seed, 2))
+    vals = []
+    for c in range(n_vals):
+        r = rand64(seed, 10 + c, idx)
+        vals.append(r if val_dtype == torch.int64 else (r >> 32).to(torch.int32))
+    return keys, vals
+
+
 def sparse_unique64(seed: int = 42, n_build: int = 1 << 24, n_probe: int = 1 << 29,
                     match_per_mille: int = 900, device="cpu") -> JoinInput:
     """Large sparse join: unique int64 build keys spread over the full 64-bit range,

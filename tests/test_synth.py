@@ -141,3 +141,10 @@ def test_wide_join_shape_and_match_rate():
         assert c.dtype == torch.int32
     w64 = synth.wide_join(seed=3, n_build=100, n_probe=1000, key_dtype=torch.int64, col_dtype=torch.int64)
     assert w64.probe_keys.dtype == torch.int64 and w64.meta["probe_cols"][2].dtype == torch.int64
+
+
+def test_groupby_input_groups():
+    k, vals = synth.groupby_input(seed=3, n=200000, groups=777)
+    assert k.dtype == torch.int32 and torch.unique(k).numel() == 777 and len(vals) == 2
+    k64, _ = synth.groupby_input(seed=3, n=50000, groups=40000, key_dtype=torch.int64)
+    assert k64.dtype == torch.int64 and torch.unique(k64).numel() > 35000  # ~ 40000 * (1 - e^-1.25)
