@@ -163,6 +163,7 @@ __global__ void __launch_bounds__(256) k_batch_unique(const Item *__restrict__ i
 template <typename K, typename P>
 struct BatchDirectTab {
   static constexpr bool kHashed = false;
+  static constexpr bool kRuns = false;
   const Slot<K, P> *slots;
   uint64_t mn, range;
   __device__ __forceinline__ uint32_t lookup(K key, uint32_t &first, uint64_t &psum) const {
@@ -185,6 +186,7 @@ struct BatchDirectTab {
 template <typename K, typename P>
 struct BatchHashTab {
   static constexpr bool kHashed = true;
+  static constexpr bool kRuns = false;
   using SlotT = Slot<K, P>;
   using Index = uint64_t;
   const Slot<K, P> *slots;

@@ -122,7 +122,9 @@ __device__ __forceinline__ void probe_load(ProbeRegs<IPT, K, PS> &r, const K *__
 //    every row is loaded before any is inspected, so a thread keeps IPT random
 //    loads in flight; only rows whose walk is not finished load again, and a
 //    unique table stops a walk at its first match.
-//  * other tables expose lookup(key, first_rowid, payload_sum) -> count.
+//  * other tables expose lookup(key, first, payload_sum) -> count, where
+//    `first` is the first match's row id, or with Tab::kRuns the start of the
+//    key's contiguous run of rows (emit_matches).
 template <int NT, int IPT, class Tab, typename K, typename PS>
 __device__ __forceinline__ void count_matches(const Tab &tab, const ProbeRegs<IPT, K, PS> &r,
                                               uint32_t (&cnt)[IPT], uint32_t (&first)[IPT],
@@ -195,6 +197,23 @@ __device__ __forceinline__ void count_matches(const Tab &tab, const ProbeRegs<IP
   }
 }
 
+// Calls f(build_rowid) for each of the `cnt` matches of a probe row whose
+// lookup gave `first`. Tables that keep a key's rows contiguous (Tab::kRuns)
+// return the start of the run in `first` and expose row_at(i), so the matches
+// are read straight from the run; other tables return the first match's row
+// id and walk again (for_each) when there are more.
+template <class Tab, typename K, class F>
+__device__ __forceinline__ void emit_matches(const Tab &tab, K key, uint32_t cnt, uint32_t first, F f) {
+  if constexpr (Tab::kRuns) {
+    for (uint32_t j = 0; j < cnt; ++j) f(tab.row_at(first + j));
+  } else {
+    if (cnt == 1)
+      f(first);
+    else if (cnt > 1)
+      tab.for_each(key, f);
+  }
+}
+
 // Probe the loaded rows against `tab` and materialize the matches. Tables also
 // provide  template <class F> void for_each(K key, F f) const  (f(build_rowid)
 // for every match) for rows with more than one match. Match totals are 64-bit:
@@ -240,27 +259,18 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
       if (tk == 0) continue;
       if (tk > SCAP) {
         uint64_t pos = base + done + ok;
-        if (cnt[k] == 1) {
-          put_pair(o, pos, first[k], r.rid[k]);
-        } else if (cnt[k] > 1) {
-          const uint32_t rr = r.rid[k];
-          tab.for_each(r.key[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
-        }
+        const uint32_t rr = r.rid[k];
+        emit_matches(tab, r.key[k], cnt[k], first[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
         done += tk;
         continue;
       }
       uint32_t pos = static_cast<uint32_t>(ok);
-      if (cnt[k] == 1) {
-        L.b[pos] = first[k];
-        L.p[pos] = r.rid[k];
-      } else if (cnt[k] > 1) {
-        const uint32_t rr = r.rid[k];
-        tab.for_each(r.key[k], [&](uint32_t b) {
-          L.b[pos] = b;
-          L.p[pos] = rr;
-          ++pos;
-        });
-      }
+      const uint32_t rr = r.rid[k];
+      emit_matches(tab, r.key[k], cnt[k], first[k], [&](uint32_t b) {
+        L.b[pos] = b;
+        L.p[pos] = rr;
+        ++pos;
+      });
       __syncthreads();
       for (uint32_t i = threadIdx.x; i < tk; i += NT) put_pair(o, base + done + i, L.b[i], L.p[i]);
       __syncthreads();
@@ -271,18 +281,12 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
   uint32_t pos = static_cast<uint32_t>(fill + off);
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
-    if (cnt[k] == 1) {
-      L.b[pos] = first[k];
-      L.p[pos] = r.rid[k];
+    const uint32_t rr = r.rid[k];
+    emit_matches(tab, r.key[k], cnt[k], first[k], [&](uint32_t b) {
+      L.b[pos] = b;
+      L.p[pos] = rr;
       ++pos;
-    } else if (cnt[k] > 1) {
-      const uint32_t rr = r.rid[k];
-      tab.for_each(r.key[k], [&](uint32_t b) {
-        L.b[pos] = b;
-        L.p[pos] = rr;
-        ++pos;
-      });
-    }
+    });
   }
   __syncthreads();
   fill += total;

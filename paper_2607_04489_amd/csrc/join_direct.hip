@@ -19,6 +19,7 @@ constexpr int kSCAP = 4096;
 template <typename K, typename PB>
 struct DirectTab {
   static constexpr bool kHashed = false;
+  static constexpr bool kRuns = true;
   uint64_t min;  // as two's-complement bits
   uint64_t range;
   const uint32_t *__restrict__ end;  // end offset of each key value's run
@@ -32,13 +33,15 @@ struct DirectTab {
     e = end[d];
     return true;
   }
+  // `first` receives the start of the key value's run (kRuns)
   __device__ __forceinline__ uint32_t lookup(K key, uint32_t &first, uint64_t &psum) const {
     uint32_t s, e;
     if (!run(key, s, e) || s == e) return 0;
-    first = rowid[s];
+    first = s;
     for (uint32_t t = s; t < e; ++t) psum += static_cast<uint64_t>(sext(pay[t]));
     return e - s;
   }
+  __device__ __forceinline__ uint32_t row_at(uint32_t i) const { return rowid[i]; }
   template <class F>
   __device__ __forceinline__ void for_each(K key, F f) const {
     uint32_t s, e;

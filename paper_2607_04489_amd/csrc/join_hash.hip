@@ -23,6 +23,7 @@ constexpr int kSCAP = 4096;
 template <typename K, typename PB>
 struct HashTab {
   static constexpr bool kHashed = true;
+  static constexpr bool kRuns = false;
   using SlotT = Slot<K, PB>;
   using Index = uint64_t;  // a table may hold more than 2^32 slots
   const Slot<K, PB> *__restrict__ slots;

@@ -407,6 +407,7 @@ struct LdsSlot {
 template <typename K, typename PB>
 struct LdsTab {
   static constexpr bool kHashed = false;
+  static constexpr bool kRuns = false;
   using SlotT = LdsSlot<K, PB>;
   K *tk;
   uint32_t *tr;
@@ -460,6 +461,7 @@ __host__ __device__ constexpr uint32_t lds_max_slots() {
 // stops at its key's slot, and its matches are one contiguous run.
 struct GrpTab {
   static constexpr bool kHashed = false;
+  static constexpr bool kRuns = true;
   const unsigned long long *w;
   const uint32_t *rid;
   const uint64_t *psum;
@@ -481,15 +483,17 @@ struct GrpTab {
       }
     }
   }
+  // `first` receives the start of the key's run of rows (kRuns)
   __device__ __forceinline__ uint32_t lookup(int32_t key, uint32_t &first, uint64_t &ps) const {
     uint32_t st = 0;
     const uint32_t c = find(key, st);
     if (c) {
-      first = rid[st];
+      first = st;
       ps += psum[st];
     }
     return c;
   }
+  __device__ __forceinline__ uint32_t row_at(uint32_t i) const { return rid[i]; }
   template <class F>
   __device__ __forceinline__ void for_each(int32_t key, F f) const {
     uint32_t st = 0;
@@ -1151,6 +1155,7 @@ __device__ __forceinline__ uint32_t fastrange32(uint64_t h, uint32_t n) {
 template <typename K, typename PB>
 struct CacheTab {
   static constexpr bool kHashed = true;
+  static constexpr bool kRuns = false;
   using SlotT = Slot<K, PB>;
   using Index = uint32_t;  // regions hold fewer than 2^32 slots
   const Slot<K, PB> *__restrict__ slots;
