@@ -243,6 +243,57 @@ int eiger_join_wide(eiger_column build_keys, const eiger_column *build_cols, int
                     int64_t out_capacity, int64_t *out_count, int32_t *out_materialized, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* ---- group-by ---------------------------------------------------------------
+ * Groups of a key column with a row count and the sum (mod 2^64, values
+ * sign-extended) of up to two value columns per group (Section 3.3: group-by
+ * algorithms). The algorithm is picked from the HLL++ distinct-count estimate
+ * of the keys (Section 4.1: the number of groups decides, and sizes the hash
+ * table; Section 5.3.2: "Auto"):
+ *  EIGER_GB_HASH       one NDV-sized open-addressing table of groups in HBM;
+ *                      each workgroup pre-aggregates its rows in LDS first
+ *  EIGER_GB_PARTITION  rows partitioned on the key hash (values carried), then
+ *                      one LDS table per partition, written out directly
+ */
+typedef enum { EIGER_GB_HASH = 0, EIGER_GB_PARTITION = 1 } eiger_groupby_variant;
+#define EIGER_GB_NO_SENTINEL 1u /* plan.flags: int64 keys cover both ends of the domain (unsupported) */
+
+typedef struct {
+    int32_t variant;          /* eiger_groupby_variant */
+    int32_t radix_bits;       /* PARTITION: 2^radix_bits partitions (1..18; one pass up to 9 bits) */
+    int32_t key_dtype;
+    uint32_t flags;           /* EIGER_GB_* */
+    int64_t slots;            /* slots of the global group table (power of two >= 1024) */
+    int64_t predicted_groups; /* the distinct-count estimate the plan used */
+    int64_t sentinel;         /* a value no key takes: marks empty slots */
+    int64_t reserved[2];
+} eiger_groupby_plan_t;
+
+/* Plan a group-by from the key column's statistics. selector: EIGER_SEL_RULE
+ * (HASH up to 2^18 estimated groups, else PARTITION with about 512 groups per
+ * partition; the global table gets twice the estimate in slots) or
+ * EIGER_SEL_FORCED (variant and radix_bits from `forced`). Host only. */
+int eiger_groupby_plan(const eiger_stats_t *keys, int32_t selector, const eiger_groupby_plan_t *forced,
+                       eiger_groupby_plan_t *out);
+
+int eiger_groupby_workspace_size(const eiger_groupby_plan_t *plan, eiger_column keys, const eiger_column *vals,
+                                 int32_t n_vals, size_t *bytes);
+
+/*
+ * Group-by of `keys` (DEVICE, int32/int64) with 0..2 value columns (HOST array
+ * of DEVICE int32/int64 columns of the same length). Group t (in no particular
+ * order): out_keys[t] (key dtype), out_counts[t] = its rows, out_sums[c][t] =
+ * the sum of vals[c] over its rows (int64, mod 2^64). out_* are DEVICE arrays
+ * of out_capacity entries (out_sums: HOST array of DEVICE pointers);
+ * out_capacity == 0 counts the groups only. *out_groups (HOST) = number of
+ * groups. EIGER_ERR_CAPACITY when the groups exceed out_capacity;
+ * EIGER_ERR_TOO_LARGE when they exceed plan.slots (the estimate was too low:
+ * plan again with more slots); EIGER_ERR_UNSUPPORTED for int64 keys that take
+ * both INT64_MIN and INT64_MAX. Synchronizes `stream`.
+ */
+int eiger_groupby(eiger_column keys, const eiger_column *vals, int32_t n_vals, const eiger_groupby_plan_t *plan,
+                  void *out_keys, int64_t *out_counts, int64_t *const *out_sums, int64_t out_capacity,
+                  int64_t *out_groups, void *ws, size_t ws_bytes, void *stream);
+
 /* Bytes of the fixed device scratch array behind eiger_join_noalloc (64 MiB). */
 #define EIGER_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 

@@ -77,6 +77,23 @@ class PlanT(ctypes.Structure):
         return d
 
 
+class GroupByPlanT(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("radix_bits", ctypes.c_int32), ("key_dtype", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("slots", ctypes.c_int64), ("predicted_groups", ctypes.c_int64),
+                ("sentinel", ctypes.c_int64), ("reserved", ctypes.c_int64 * 2)]
+
+    def describe(self) -> dict:
+        d = {"variant": GB_NAMES.get(self.variant, str(self.variant)), "slots": int(self.slots),
+             "predicted_groups": int(self.predicted_groups)}
+        if self.variant == GB_PARTITION:
+            d["radix_bits"] = int(self.radix_bits)
+        return d
+
+
+GB_HASH, GB_PARTITION = 0, 1
+GB_NAMES = {GB_HASH: "hash", GB_PARTITION: "partition"}
+
+
 class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
                 ("total_ms", ctypes.c_double)]
@@ -119,6 +136,14 @@ def lib():
         L.eiger_join_wide.restype = ctypes.c_int
         L.eiger_calibrate.argtypes = [i32, vp, vp, i64, i64, ctypes.POINTER(ctypes.c_double), vp]
         L.eiger_calibrate.restype = ctypes.c_int
+        L.eiger_groupby_plan.argtypes = [ctypes.POINTER(StatsT), i32, ctypes.POINTER(GroupByPlanT),
+                                         ctypes.POINTER(GroupByPlanT)]
+        L.eiger_groupby_plan.restype = ctypes.c_int
+        L.eiger_groupby_workspace_size.argtypes = [ctypes.POINTER(GroupByPlanT), Column, vp, i32, ctypes.POINTER(sz)]
+        L.eiger_groupby_workspace_size.restype = ctypes.c_int
+        L.eiger_groupby.argtypes = [Column, vp, i32, ctypes.POINTER(GroupByPlanT), vp, vp, vp, i64,
+                                    ctypes.POINTER(i64), vp, sz, vp]
+        L.eiger_groupby.restype = ctypes.c_int
         L.eiger_join_noalloc.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.eiger_join_noalloc.restype = ctypes.c_int
@@ -300,6 +325,75 @@ def join(bk, bp, pk, pp, plan: PlanT, capacity: Optional[int] = None, stream=Non
         rc = run(ob, op, capacity)
     _check(rc, cnt.value)
     return JoinResult(ob[: cnt.value], op[: cnt.value], cnt.value, cs.value)
+
+
+def groupby_plan(key_stats: Stats, selector: int = SEL_RULE, forced: Optional[GroupByPlanT] = None) -> GroupByPlanT:
+    """eiger_groupby_plan: HASH or PARTITION from the keys' statistics (HLL estimate)."""
+    out = GroupByPlanT()
+    _check(lib().eiger_groupby_plan(ctypes.byref(key_stats.raw), selector,
+                                    ctypes.byref(forced) if forced is not None else None, ctypes.byref(out)))
+    return out
+
+
+def make_groupby_plan(variant: int, radix_bits: int = 0) -> GroupByPlanT:
+    p = GroupByPlanT()
+    p.variant, p.radix_bits = variant, radix_bits
+    return p
+
+
+@dataclass
+class GroupByResult:
+    keys: object     # group keys (key dtype), length groups
+    counts: object   # torch.int64
+    sums: list       # torch.int64 per value column
+    groups: int
+    plan: GroupByPlanT
+
+
+def groupby(keys, vals, plan: Optional[GroupByPlanT] = None, capacity: Optional[int] = None, stream=None,
+            workspace=None) -> GroupByResult:
+    """eiger_groupby: groups of `keys` with counts and sums of the value columns.
+    Without a plan, the keys' statistics are computed and the rule planner picks
+    one. A plan whose table turns out too small (the estimate was low) is run
+    again with a table of twice the rows; a result above `capacity` is run again
+    at its exact size."""
+    import torch
+    if plan is None:
+        plan = groupby_plan(stats(keys, stream))
+    kc = column(keys)
+    arr = (Column * max(len(vals), 1))()
+    for i, t in enumerate(vals):
+        arr[i] = column(t)
+    groups = ctypes.c_int64()
+
+    def run(pl, cap):
+        need = ctypes.c_size_t()
+        _check(lib().eiger_groupby_workspace_size(ctypes.byref(pl), kc, arr, len(vals), ctypes.byref(need)))
+        ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value,
+                                                                                                     keys.device)
+        ok = torch.empty(max(cap, 1), dtype=keys.dtype, device=keys.device)
+        oc = torch.empty(max(cap, 1), dtype=torch.int64, device=keys.device)
+        osum = [torch.empty(max(cap, 1), dtype=torch.int64, device=keys.device) for _ in vals]
+        ptrs = (ctypes.c_void_p * max(len(vals), 1))(*[t.data_ptr() for t in osum])
+        rc = lib().eiger_groupby(kc, arr, len(vals), ctypes.byref(pl), ctypes.c_void_p(ok.data_ptr()),
+                                 ctypes.c_void_p(oc.data_ptr()), ptrs, cap, ctypes.byref(groups),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+        return rc, ok, oc, osum
+
+    if capacity is None:
+        capacity = min(keys.numel(), int(plan.predicted_groups * 1.25) + 1024)
+    rc, ok, oc, osum = run(plan, capacity)
+    if rc == EIGER_ERR_TOO_LARGE:
+        slots = 1024
+        while slots < 2 * keys.numel() + 1:
+            slots <<= 1
+        plan.slots = slots
+        rc, ok, oc, osum = run(plan, capacity)
+    if rc == EIGER_ERR_CAPACITY:
+        rc, ok, oc, osum = run(plan, groups.value)
+    _check(rc)
+    g = groups.value
+    return GroupByResult(ok[:g], oc[:g], [t[:g] for t in osum], g, plan)
 
 
 MAT_GFUR, MAT_GFTR, MAT_AUTO = 0, 1, 2

@@ -1,0 +1,510 @@
+// groupby.hip -- group-by with a count and per-column sums, hash-based or
+// partition-based, chosen from the HLL distinct-count estimate of the key
+// column (Section 3.3: group-by algorithms; Section 4.1: the number of groups,
+// estimated with HLL++ before the operator runs, picks the algorithm and sizes
+// the hash table; Section 5.3.2: the "Auto" series).
+//
+//  HASH       one open-addressing table of groups in HBM, sized from the
+//             estimate. Every workgroup first aggregates its rows in an LDS
+//             table (so a few hot groups cost one global update per workgroup,
+//             not one per row); rows whose group does not fit in LDS go to the
+//             global table; at the end each workgroup merges its LDS groups
+//             into the global table, which is then compacted into the output.
+//  PARTITION  rows partitioned on the top bits of the key hash (values
+//             carried along), then one workgroup per partition aggregates it in
+//             LDS and writes its groups straight out (partitions own disjoint
+//             keys). A partition with more groups than its LDS table spills
+//             into the global table, and its LDS groups are merged there too.
+// Group keys live in the tables as sign-extended 64-bit words; a value that is
+// not a key (the plan's sentinel) marks empty slots, so a key is claimed with
+// one 64-bit CAS.
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "variants.hpp"
+
+namespace eiger {
+
+int radix_partition_carry(int32_t kdt, const void *keys, uint64_t n, const WordCols &cols, int bits, int passes,
+                          Workspace &ws, PartitionedSide *out, hipStream_t s, bool run);
+
+namespace {
+
+constexpr int kGNT = 256;
+constexpr uint32_t kGLds = 2048;            // LDS table slots (power of two)
+constexpr uint32_t kGLdsOpen = kGLds / 2;   // new groups an LDS table accepts
+constexpr int kGMaxVals = 2;
+constexpr uint32_t kGChunk = 1u << 16;      // rows per workgroup chunk (HASH)
+constexpr double kGbHashMaxGroups = 1 << 18;  // rule: HASH up to this many estimated groups
+constexpr double kGbGroupsPerPartition = 512.0;
+
+struct GbGlobal {
+  unsigned long long *key;
+  unsigned long long *cnt;
+  unsigned long long *sum[kGMaxVals];
+  uint64_t mask;
+  unsigned long long sentinel;
+  uint32_t *overflow;
+};
+
+struct GbVals {
+  const uint32_t *lo[kGMaxVals];
+  const uint32_t *hi[kGMaxVals];  // null: 4-byte column (sign-extended)
+  uint32_t stride[kGMaxVals];
+  int n;
+};
+
+struct GbLds {
+  unsigned long long key[kGLds];
+  unsigned long long cnt[kGLds];
+  unsigned long long sum[kGMaxVals][kGLds];
+  uint32_t used;
+  uint32_t spilled;
+};
+
+__device__ __forceinline__ uint64_t val_at(const GbVals &v, int c, uint64_t i) {
+  const uint64_t at = i * v.stride[c];
+  const uint32_t lo = v.lo[c][at];
+  if (v.hi[c]) return (uint64_t(v.hi[c][at]) << 32) | lo;
+  return static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(lo)));
+}
+
+// Slot of key k in the global table, claiming an empty one if needed; -1 when
+// the whole table was walked (more groups than slots: *overflow is set).
+__device__ __forceinline__ int64_t global_slot(const GbGlobal &t, unsigned long long k) {
+  uint64_t s = fmix64(k) & t.mask;
+  for (uint64_t step = 0; step <= t.mask; ++step) {
+    // a slot changes once, from the sentinel to a key: any other value read is final
+    const unsigned long long cur = __atomic_load_n(&t.key[s], __ATOMIC_RELAXED);
+    if (cur == k) return static_cast<int64_t>(s);
+    if (cur == t.sentinel) {
+      const unsigned long long old = atomicCAS(&t.key[s], t.sentinel, k);
+      if (old == t.sentinel || old == k) return static_cast<int64_t>(s);
+    }
+    s = (s + 1) & t.mask;
+  }
+  atomicOr(t.overflow, 1u);
+  return -1;
+}
+
+__device__ __forceinline__ void global_add(const GbGlobal &t, unsigned long long k, unsigned long long c,
+                                           const unsigned long long *sums, int nv) {
+  const int64_t s = global_slot(t, k);
+  if (s < 0) return;
+  atomicAdd(&t.cnt[s], c);
+  for (int v = 0; v < nv; ++v) atomicAdd(&t.sum[v][s], sums[v]);
+}
+
+// LDS slot of key k, claiming an empty slot while the table takes new groups;
+// -1: not in the table and the table is closed (the row goes global).
+__device__ __forceinline__ int lds_slot(GbLds &L, unsigned long long k, unsigned long long sentinel) {
+  uint32_t s = static_cast<uint32_t>(fmix64(k)) & (kGLds - 1);
+  for (uint32_t step = 0; step < kGLds; ++step) {
+    const unsigned long long cur = L.key[s];
+    if (cur == k) return static_cast<int>(s);
+    if (cur == sentinel) {
+      if (atomicAdd(&L.used, 1u) >= kGLdsOpen) return -1;  // closed for new groups
+      const unsigned long long old = atomicCAS(&L.key[s], sentinel, k);
+      if (old == sentinel || old == k) return static_cast<int>(s);
+    }
+    s = (s + 1) & (kGLds - 1);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void lds_clear(GbLds &L, unsigned long long sentinel, int nv) {
+  for (uint32_t i = threadIdx.x; i < kGLds; i += kGNT) {
+    L.key[i] = sentinel;
+    L.cnt[i] = 0;
+    for (int v = 0; v < nv; ++v) L.sum[v][i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    L.used = 0;
+    L.spilled = 0;
+  }
+  __syncthreads();
+}
+
+// Aggregate rows [lo, hi) into the LDS table (rows that do not fit go global).
+template <typename K>
+__device__ __forceinline__ void aggregate_rows(GbLds &L, const GbGlobal &g, const K *__restrict__ keys,
+                                               const GbVals &vals, uint64_t lo, uint64_t hi) {
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kGNT) {
+    const unsigned long long k = static_cast<unsigned long long>(sext(keys[i]));
+    unsigned long long sv[kGMaxVals];
+    for (int v = 0; v < vals.n; ++v) sv[v] = val_at(vals, v, i);
+    const int s = lds_slot(L, k, g.sentinel);
+    if (s >= 0) {
+      atomicAdd(&L.cnt[s], 1ull);
+      for (int v = 0; v < vals.n; ++v) atomicAdd(&L.sum[v][s], sv[v]);
+    } else {
+      L.spilled = 1;
+      global_add(g, k, 1ull, sv, vals.n);
+    }
+  }
+  __syncthreads();
+}
+
+// Merge the LDS groups into the global table.
+__device__ __forceinline__ void lds_merge(GbLds &L, const GbGlobal &g, int nv) {
+  for (uint32_t i = threadIdx.x; i < kGLds; i += kGNT) {
+    const unsigned long long k = L.key[i];
+    if (k == g.sentinel) continue;
+    unsigned long long sv[kGMaxVals];
+    for (int v = 0; v < nv; ++v) sv[v] = L.sum[v][i];
+    global_add(g, k, L.cnt[i], sv, nv);
+  }
+}
+
+struct GbOut {
+  void *keys;  // key dtype
+  unsigned long long *cnt;
+  unsigned long long *sum[kGMaxVals];
+  uint64_t cap;
+  unsigned long long *cursor;
+  int kwide;
+};
+
+__device__ __forceinline__ void put_group(const GbOut &o, uint64_t pos, unsigned long long k, unsigned long long c,
+                                          const unsigned long long *sv, int nv) {
+  if (pos >= o.cap || !o.keys) return;
+  if (o.kwide)
+    static_cast<unsigned long long *>(o.keys)[pos] = k;
+  else
+    static_cast<uint32_t *>(o.keys)[pos] = static_cast<uint32_t>(k);
+  o.cnt[pos] = c;
+  for (int v = 0; v < nv; ++v) o.sum[v][pos] = sv[v];
+}
+
+// Emit the occupied slots of one table range [lo, hi) of (key, cnt, sums) arrays,
+// one output reservation per wave.
+__device__ __forceinline__ void emit_range(const unsigned long long *key, const unsigned long long *cnt,
+                                           const unsigned long long *sum0, const unsigned long long *sum1,
+                                           uint64_t lo, uint64_t hi, unsigned long long sentinel, int nv,
+                                           const GbOut &o) {
+  const uint32_t lane = __lane_id();
+  const uint64_t wlo = lo + (threadIdx.x / 64) * 64, wstep = kGNT;
+  for (uint64_t base = wlo; base < hi; base += wstep) {
+    const uint64_t i = base + lane;
+    const bool live = i < hi && key[i] != sentinel;
+    const uint64_t m = __ballot(live);
+    if (m == 0) continue;
+    unsigned long long at = 0;
+    if (lane == 0) at = atomicAdd(o.cursor, static_cast<unsigned long long>(__popcll(m)));
+    at = __shfl(at, 0, 64);
+    if (live) {
+      unsigned long long sv[kGMaxVals] = {0, 0};
+      if (nv > 0) sv[0] = sum0[i];
+      if (nv > 1) sv[1] = sum1[i];
+      put_group(o, at + lane_prefix(m), key[i], cnt[i], sv, nv);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kGNT) k_gb_clear(GbGlobal g, int nv) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i <= g.mask; i += stride) {
+    g.key[i] = g.sentinel;
+    g.cnt[i] = 0;
+    for (int v = 0; v < nv; ++v) g.sum[v][i] = 0;
+  }
+}
+
+// HASH: chunks of kGChunk rows per workgroup, LDS pre-aggregation, merge.
+template <typename K>
+__global__ void __launch_bounds__(kGNT) k_gb_hash(const K *__restrict__ keys, uint64_t n, GbVals vals, GbGlobal g) {
+  __shared__ GbLds L;
+  for (uint64_t lo = uint64_t(blockIdx.x) * kGChunk; lo < n; lo += uint64_t(gridDim.x) * kGChunk) {
+    lds_clear(L, g.sentinel, vals.n);
+    aggregate_rows<K>(L, g, keys, vals, lo, min(n, lo + kGChunk));
+    lds_merge(L, g, vals.n);
+    __syncthreads();
+  }
+}
+
+// PARTITION: one partition per work item; groups written out directly unless
+// the partition spilled, in which case they are merged into the global table.
+template <typename K>
+__global__ void __launch_bounds__(kGNT)
+    k_gb_partition(const K *__restrict__ keys, GbVals vals, const uint32_t *__restrict__ off, uint32_t F, GbGlobal g,
+                   GbOut o) {
+  __shared__ GbLds L;
+  for (uint32_t p = blockIdx.x; p < F; p += gridDim.x) {
+    const uint32_t lo = off[p], hi = off[p + 1];
+    if (lo == hi) continue;
+    lds_clear(L, g.sentinel, vals.n);
+    aggregate_rows<K>(L, g, keys, vals, lo, hi);
+    if (L.spilled) {
+      lds_merge(L, g, vals.n);
+    } else {
+      emit_range(L.key, L.cnt, L.sum[0], L.sum[1], 0, kGLds, g.sentinel, vals.n, o);
+    }
+    __syncthreads();
+  }
+}
+
+// Compaction of the global table into the output.
+__global__ void __launch_bounds__(kGNT) k_gb_emit(GbGlobal g, int nv, GbOut o) {
+  const uint64_t slots = g.mask + 1;
+  const uint64_t per = (slots + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = uint64_t(blockIdx.x) * per, hi = min(slots, lo + per);
+  emit_range(g.key, g.cnt, g.sum[0], g.sum[1], lo, hi, g.sentinel, nv, o);
+}
+
+int gb_sentinel(const eiger_groupby_plan_t &p, unsigned long long *out) {
+  *out = static_cast<unsigned long long>(p.sentinel);
+  return EIGER_OK;
+}
+
+uint64_t gb_slots(double groups) {
+  uint64_t s = 1024;
+  while (static_cast<double>(s) < 2.0 * groups + 1.0) s <<= 1;
+  return s;
+}
+
+struct GbLayout {
+  GbGlobal g;
+  unsigned long long *cursor;
+  uint32_t *overflow;
+};
+
+GbLayout gb_layout(Workspace &ws, uint64_t slots, int nv, unsigned long long sentinel) {
+  GbLayout L{};
+  L.g.key = ws.take<unsigned long long>(slots);
+  L.g.cnt = ws.take<unsigned long long>(slots);
+  for (int v = 0; v < kGMaxVals; ++v) L.g.sum[v] = v < nv ? ws.take<unsigned long long>(slots) : nullptr;
+  L.g.mask = slots - 1;
+  L.g.sentinel = sentinel;
+  L.cursor = ws.take<unsigned long long>(1);
+  L.overflow = ws.take<uint32_t>(1);
+  L.g.overflow = L.overflow;
+  return L;
+}
+
+GbVals gb_vals(const eiger_column *vals, int32_t nv) {
+  GbVals v{};
+  v.n = nv;
+  for (int32_t c = 0; c < nv; ++c) {
+    const uint32_t *base = static_cast<const uint32_t *>(vals[c].data);
+    const bool wide = vals[c].dtype == EIGER_INT64;
+    v.lo[c] = base;
+    v.hi[c] = wide && base ? base + 1 : nullptr;
+    v.stride[c] = wide ? 2 : 1;
+  }
+  return v;
+}
+
+// Lays out and (with a workspace base) enqueues the group-by.
+template <typename K>
+int gb_impl(const eiger_column &keys, const eiger_column *vals, int32_t nv, const eiger_groupby_plan_t &plan,
+            const GbOut &out_in, Workspace &ws, GbLayout *lay, hipStream_t s) {
+  const uint64_t n = static_cast<uint64_t>(keys.n);
+  unsigned long long sentinel;
+  gb_sentinel(plan, &sentinel);
+  *lay = gb_layout(ws, static_cast<uint64_t>(plan.slots), nv, sentinel);
+  PartitionedSide part{};
+  WordCols wc{};
+  if (plan.variant == EIGER_GB_PARTITION) {
+    for (int32_t c = 0; c < nv; ++c) {
+      const uint32_t *base = static_cast<const uint32_t *>(vals[c].data);
+      if (vals[c].dtype == EIGER_INT64) {
+        wc.src[wc.n] = base;
+        wc.stride[wc.n++] = 2;
+        wc.src[wc.n] = base ? base + 1 : nullptr;
+        wc.stride[wc.n++] = 2;
+      } else {
+        wc.src[wc.n] = base;
+        wc.stride[wc.n++] = 1;
+      }
+    }
+    int rc = radix_partition_carry(keys.dtype, keys.data, n, wc, plan.radix_bits, plan.radix_bits > 9 ? 2 : 1, ws,
+                                   &part, n > 0 ? s : nullptr, n > 0);
+    if (rc) return rc;
+  }
+  if (!ws.base) return EIGER_OK;
+  const GbGlobal &g = lay->g;
+  GbOut o = out_in;
+  o.cursor = lay->cursor;
+  int rc;
+  if ((rc = fill_u64(reinterpret_cast<uint64_t *>(lay->cursor), 1, 0, s))) return rc;
+  if ((rc = fill_u32(lay->overflow, 1, 0, s))) return rc;
+  const unsigned cus = static_cast<unsigned>(device_cu_count());
+  EIGER_LAUNCH("groupby_clear", k_gb_clear, dim3(std::min<uint64_t>((plan.slots + kGNT - 1) / kGNT, cus * 8)),
+               dim3(kGNT), 0, s, g, nv);
+  if (n == 0) return EIGER_OK;
+  if (plan.variant == EIGER_GB_HASH) {
+    const GbVals v = gb_vals(vals, nv);
+    const uint64_t chunks = (n + kGChunk - 1) / kGChunk;
+    EIGER_LAUNCH("groupby_hash", k_gb_hash<K>, dim3(static_cast<unsigned>(std::min<uint64_t>(chunks, cus * 2))),
+                 dim3(kGNT), 0, s, static_cast<const K *>(keys.data), n, v, g);
+  } else {
+    // partitioned values: one word array per lane (stride 1)
+    GbVals v{};
+    v.n = nv;
+    int w = 0;
+    for (int32_t c = 0; c < nv; ++c) {
+      const bool wide = vals[c].dtype == EIGER_INT64;
+      v.lo[c] = part.words[w];
+      v.hi[c] = wide ? part.words[w + 1] : nullptr;
+      v.stride[c] = 1;
+      w += wide ? 2 : 1;
+    }
+    const uint32_t F = 1u << plan.radix_bits;
+    EIGER_LAUNCH("groupby_partition", k_gb_partition<K>, dim3(std::min<uint32_t>(F, cus * 2)), dim3(kGNT), 0, s,
+                 static_cast<const K *>(part.keys), v, part.off, F, g, o);
+  }
+  EIGER_LAUNCH("groupby_emit", k_gb_emit, dim3(static_cast<unsigned>(std::min<uint64_t>(
+                                              (plan.slots + 4095) / 4096, cus * 4))),
+               dim3(kGNT), 0, s, g, nv, o);
+  return EIGER_OK;
+}
+
+int gb_run(const eiger_column &keys, const eiger_column *vals, int32_t nv, const eiger_groupby_plan_t &plan,
+           const GbOut &o, Workspace &ws, GbLayout *lay, hipStream_t s) {
+  if (keys.dtype == EIGER_INT64) return gb_impl<int64_t>(keys, vals, nv, plan, o, ws, lay, s);
+  return gb_impl<int32_t>(keys, vals, nv, plan, o, ws, lay, s);
+}
+
+int gb_check(const eiger_column &keys, const eiger_column *vals, int32_t nv, const eiger_groupby_plan_t *plan) {
+  if (!plan) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: plan is NULL");
+  if (keys.dtype != EIGER_INT32 && keys.dtype != EIGER_INT64)
+    return fail(EIGER_ERR_DTYPE, "eiger_groupby: key dtype must be EIGER_INT32 or EIGER_INT64");
+  if (keys.dtype != plan->key_dtype) return fail(EIGER_ERR_DTYPE, "eiger_groupby: plan.key_dtype differs from the keys");
+  if (keys.n < 0) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: negative row count");
+  if (keys.n > EIGER_MAX_ROWS) return fail(EIGER_ERR_TOO_LARGE, "eiger_groupby: more than EIGER_MAX_ROWS rows");
+  if (keys.n > 0 && (!keys.data || reinterpret_cast<uintptr_t>(keys.data) % dtype_size(keys.dtype)))
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: keys NULL or misaligned");
+  if (nv < 0 || nv > kGMaxVals) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: 0 to 2 value columns");
+  if (nv > 0 && !vals) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: NULL value column array");
+  for (int32_t c = 0; c < nv; ++c) {
+    if (vals[c].dtype != EIGER_INT32 && vals[c].dtype != EIGER_INT64)
+      return fail(EIGER_ERR_DTYPE, "eiger_groupby: value dtype must be EIGER_INT32 or EIGER_INT64");
+    if (vals[c].n != keys.n) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: value column length differs");
+    if (keys.n > 0 && (!vals[c].data || reinterpret_cast<uintptr_t>(vals[c].data) % dtype_size(vals[c].dtype)))
+      return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: value column NULL or misaligned");
+  }
+  if (plan->variant != EIGER_GB_HASH && plan->variant != EIGER_GB_PARTITION)
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: plan.variant is not an eiger_groupby_variant");
+  if (plan->slots < 1024 || (plan->slots & (plan->slots - 1)))
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: plan.slots must be a power of two >= 1024");
+  if (plan->variant == EIGER_GB_PARTITION && (plan->radix_bits < 1 || plan->radix_bits > 18))
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: plan.radix_bits must be in [1, 18]");
+  if (plan->flags & EIGER_GB_NO_SENTINEL)
+    return fail(EIGER_ERR_UNSUPPORTED, "eiger_groupby: the keys span the whole int64 domain (no free value marks "
+                                       "empty slots)");
+  return EIGER_OK;
+}
+
+}  // namespace
+}  // namespace eiger
+
+using namespace eiger;
+
+extern "C" int eiger_groupby_plan(const eiger_stats_t *keys, int32_t selector, const eiger_groupby_plan_t *forced,
+                                  eiger_groupby_plan_t *out) {
+  if (!keys || !out) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby_plan: NULL argument");
+  if (keys->dtype != EIGER_INT32 && keys->dtype != EIGER_INT64)
+    return fail(EIGER_ERR_DTYPE, "eiger_groupby_plan: unsupported key dtype");
+  eiger_groupby_plan_t p{};
+  p.key_dtype = keys->dtype;
+  // a value outside [min, max] marks empty slots; int32 keys never reach INT64_MIN
+  if (keys->dtype == EIGER_INT32 || keys->n == 0 || keys->min > INT64_MIN) {
+    p.sentinel = INT64_MIN;
+  } else if (keys->max < INT64_MAX) {
+    p.sentinel = INT64_MAX;
+  } else {
+    p.flags |= EIGER_GB_NO_SENTINEL;
+  }
+  const double est = std::max(1.0, std::min(keys->ndv, static_cast<double>(std::max<int64_t>(keys->n, 1))));
+  p.predicted_groups = static_cast<int64_t>(std::llround(est));
+  if (selector == EIGER_SEL_FORCED) {
+    if (!forced) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby_plan: EIGER_SEL_FORCED needs `forced`");
+    p.variant = forced->variant;
+    p.radix_bits = forced->radix_bits;
+  } else if (selector == EIGER_SEL_RULE || selector == EIGER_SEL_LEARNED) {
+    p.variant = est <= kGbHashMaxGroups ? EIGER_GB_HASH : EIGER_GB_PARTITION;
+    p.radix_bits = 0;
+  } else {
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby_plan: selector must be EIGER_SEL_RULE or EIGER_SEL_FORCED");
+  }
+  if (p.variant == EIGER_GB_PARTITION && (p.radix_bits < 1 || p.radix_bits > 18)) {
+    int bits = 1;
+    while (bits < 18 && est / std::ldexp(1.0, bits) > kGbGroupsPerPartition) ++bits;
+    p.radix_bits = bits;
+  }
+  // the global table: NDV-sized (twice the estimate); the partitioned variant
+  // only spills into it
+  p.slots = static_cast<int64_t>(gb_slots(p.variant == EIGER_GB_HASH ? est : est / 8.0));
+  *out = p;
+  return EIGER_OK;
+}
+
+extern "C" int eiger_groupby_workspace_size(const eiger_groupby_plan_t *plan, eiger_column keys,
+                                            const eiger_column *vals, int32_t n_vals, size_t *bytes) {
+  if (!bytes) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby_workspace_size: bytes is NULL");
+  static const int64_t dummy[1] = {0};
+  eiger_column k = keys, v[kGMaxVals];
+  if (k.n > 0) k.data = dummy;
+  if (n_vals < 0 || n_vals > kGMaxVals) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: 0 to 2 value columns");
+  for (int32_t c = 0; c < n_vals; ++c) {
+    if (!vals) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: NULL value column array");
+    v[c] = vals[c];
+    if (v[c].n > 0) v[c].data = dummy;
+  }
+  int rc = gb_check(k, v, n_vals, plan);
+  if (rc) return rc;
+  Workspace ws(nullptr, 0);
+  GbLayout lay{};
+  if ((rc = gb_run(k, v, n_vals, *plan, GbOut{}, ws, &lay, nullptr))) return rc;
+  *bytes = ws.used;
+  return EIGER_OK;
+}
+
+extern "C" int eiger_groupby(eiger_column keys, const eiger_column *vals, int32_t n_vals,
+                             const eiger_groupby_plan_t *plan, void *out_keys, int64_t *out_counts,
+                             int64_t *const *out_sums, int64_t out_capacity, int64_t *out_groups, void *ws_ptr,
+                             size_t ws_bytes, void *stream) {
+  int rc = gb_check(keys, vals, n_vals, plan);
+  if (rc) return rc;
+  if (!out_groups) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: out_groups is NULL");
+  if (out_capacity < 0) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: negative out_capacity");
+  if (out_capacity > 0 && (!out_keys || !out_counts || (n_vals > 0 && !out_sums)))
+    return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: NULL output arrays");
+  for (int32_t c = 0; out_capacity > 0 && c < n_vals; ++c)
+    if (!out_sums[c]) return fail(EIGER_ERR_INVALID_ARG, "eiger_groupby: NULL sum output");
+  {
+    Workspace dry(nullptr, 0);
+    GbLayout lay{};
+    if ((rc = gb_run(keys, vals, n_vals, *plan, GbOut{}, dry, &lay, nullptr))) return rc;
+    if (!ws_ptr || dry.used > ws_bytes)
+      return fail(EIGER_ERR_WORKSPACE, "eiger_groupby: workspace too small (need " + std::to_string(dry.used) +
+                                           " bytes)");
+  }
+  GbOut o{};
+  o.keys = out_capacity > 0 ? out_keys : nullptr;
+  o.cnt = reinterpret_cast<unsigned long long *>(out_counts);
+  for (int32_t c = 0; c < n_vals; ++c)
+    o.sum[c] = out_capacity > 0 ? reinterpret_cast<unsigned long long *>(out_sums[c]) : nullptr;
+  o.cap = static_cast<uint64_t>(out_capacity);
+  o.kwide = keys.dtype == EIGER_INT64;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws(ws_ptr, ws_bytes);
+  GbLayout lay{};
+  if ((rc = gb_run(keys, vals, n_vals, *plan, o, ws, &lay, s))) return rc;
+  struct {
+    unsigned long long groups;
+    uint32_t overflow;
+  } host{};
+  EIGER_HIP(hipMemcpyAsync(&host.groups, lay.cursor, sizeof(host.groups), hipMemcpyDeviceToHost, s));
+  EIGER_HIP(hipMemcpyAsync(&host.overflow, lay.overflow, sizeof(host.overflow), hipMemcpyDeviceToHost, s));
+  EIGER_HIP(hipStreamSynchronize(s));
+  if (host.overflow)
+    return fail(EIGER_ERR_TOO_LARGE, "eiger_groupby: more groups than the plan's table slots (the distinct-count "
+                                     "estimate was low); raise plan.slots");
+  *out_groups = static_cast<int64_t>(host.groups);
+  if (host.groups > static_cast<uint64_t>(out_capacity))
+    return fail(EIGER_ERR_CAPACITY, "eiger_groupby: " + std::to_string(host.groups) + " groups exceed out_capacity " +
+                                        std::to_string(out_capacity));
+  return EIGER_OK;
+}
