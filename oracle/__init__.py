@@ -13,7 +13,9 @@ Contents (each function cites the passage of the paper it follows):
   * column_stats    -- count, min, max, HLL registers and distinct estimate
   * fmix64          -- the 64-bit hash used by the sketch
 The C part lives in ``eiger_oracle.c`` and is compiled with gcc on first use.
-The MLP reference for the learned selector lives in ``oracle.mlp``.
+The MLP reference for the learned selector lives in ``oracle.mlp``; smart key
+fusion, the order-preserving dictionary encoding and the multi-key sort and
+join live in ``oracle.skf``.
 """
 from __future__ import annotations
 

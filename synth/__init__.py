@@ -514,3 +514,49 @@ def batched_join(seed: int, j: int, log2_lo: float = 8.0, log2_hi: float = 18.0,
 def batched_joins(seed: int, n_joins: int, log2_lo: float = 8.0, log2_hi: float = 18.0, device="cpu"):
     """Joins 0 .. n_joins-1 of a batch (batched_join). Returns a list of JoinInput."""
     return [batched_join(seed, j, log2_lo, log2_hi, device) for j in range(n_joins)]
+
+
+def multikey_table(seed: int = 42, n: int = 1 << 28, n_keys: int = 4, dtype=torch.int32, narrow_bits: int = 8,
+                   sparse_ndv: int = 256, device="cpu", stream0: int = 60):
+    """Key columns of the paper's multi-key sort (Section 5.6): half of the keys
+    have a narrow value range (even positions: base + uniform [0, 2^narrow_bits),
+    base drawn per key), the other half a sparse spread of few distinct values
+    (odd positions: one of `sparse_ndv` distinct values spread over the type's
+    whole range, drawn uniformly per row). Returns a list of `n_keys` columns."""
+    dev = torch.device(device)
+    idx = torch.arange(n, dtype=torch.int64, device=dev)
+    top = 31 if dtype == torch.int32 else 62
+    cols = []
+    for c in range(n_keys):
+        r = rand64(seed, stream0 + c, idx)
+        if c % 2 == 0:
+            base = (_stream_base(seed, stream0 + 20 + c) >> 8) % ((1 << top) - (1 << narrow_bits))
+            base -= 1 << (top - 1)
+            col = base + uniform_below(r, 1 << narrow_bits)
+        else:
+            d = torch.arange(sparse_ndv, dtype=torch.int64, device=dev)
+            if dtype == torch.int32:
+                vals = bij31(d, seed + c) * 2 - (1 << 31)
+            else:
+                vals = mix64(d + _s64(_stream_base(seed, stream0 + 40 + c)))
+            col = vals[uniform_below(r, sparse_ndv)]
+        cols.append(col.to(dtype))
+    return cols
+
+
+def multikey_join(seed: int = 42, n_build: int = 1 << 16, n_probe: int = 1 << 20, n_keys: int = 2,
+                  dtype=torch.int32, narrow_bits: int = 8, sparse_ndv: int = 256, match_per_mille: int = 500,
+                  device="cpu"):
+    """Two relations joined on `n_keys` key columns drawn like multikey_table:
+    each probe row copies the key tuple of a uniformly drawn build row with
+    probability match_per_mille/1000, else draws a fresh tuple from the same
+    distribution (which may or may not occur in the build side). Returns
+    (build key columns, probe key columns)."""
+    dev = torch.device(device)
+    R = multikey_table(seed, n_build, n_keys, dtype, narrow_bits, sparse_ndv, device, stream0=60)
+    fresh = multikey_table(seed, n_probe, n_keys, dtype, narrow_bits, sparse_ndv, device, stream0=90)
+    ip = torch.arange(n_probe, dtype=torch.int64, device=dev)
+    take = uniform_below(rand64(seed, 120, ip), 1000) < match_per_mille
+    src = uniform_below(rand64(seed, 121, ip), max(n_build, 1))
+    S = [torch.where(take, r[src] if n_build else f, f) for r, f in zip(R, fresh)]
+    return R, S

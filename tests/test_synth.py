@@ -149,3 +149,23 @@ def test_groupby_input_groups():
     k64, _ = synth.groupby_input(seed=3, n=50000, groups=40000, key_dtype=torch.int64)
     # 50,000 uniform draws over 40,000 keys hit 40000 * (1 - e^-1.25) = 28,539 of them on average
     assert k64.dtype == torch.int64 and abs(torch.unique(k64).numel() - 28539) < 600
+
+
+@pytest.mark.parametrize("dtype,bits,ndv", [(torch.int32, 8, 256), (torch.int64, 12, 4096)])
+def test_multikey_table_shape(dtype, bits, ndv):
+    cols = synth.multikey_table(5, 200000, 4, dtype, bits, ndv)
+    assert len(cols) == 4 and all(c.dtype == dtype and c.numel() == 200000 for c in cols)
+    for c in (cols[0], cols[2]):       # narrow: all of the 2^bits values, none outside
+        assert int(c.max()) - int(c.min()) == (1 << bits) - 1
+    for c in (cols[1], cols[3]):       # sparse: exactly ndv values over a wide range
+        assert torch.unique(c).numel() == ndv
+        assert int(c.max()) - int(c.min()) > (1 << (30 if dtype == torch.int32 else 60))
+    again = synth.multikey_table(5, 200000, 4, dtype, bits, ndv)
+    assert all(torch.equal(a, b) for a, b in zip(cols, again))
+
+
+def test_multikey_join_match_share():
+    R, S = synth.multikey_join(3, 4096, 100000, 2, match_per_mille=500)
+    rows = set(zip(*(r.tolist() for r in R)))
+    hit = sum(t in rows for t in zip(*(s.tolist() for s in S)))
+    assert 0.48 * 100000 < hit < 0.60 * 100000
