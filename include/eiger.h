@@ -269,8 +269,9 @@ typedef struct {
 } eiger_groupby_plan_t;
 
 /* Plan a group-by from the key column's statistics. selector: EIGER_SEL_RULE
- * (HASH up to 2^18 estimated groups, else PARTITION with about 512 groups per
- * partition; the global table gets twice the estimate in slots) or
+ * (HASH up to 1024 estimated groups, what one LDS table holds, else PARTITION
+ * with about 512 groups per partition; the global table gets twice the
+ * estimate in slots) or
  * EIGER_SEL_FORCED (variant and radix_bits from `forced`). Host only. */
 int eiger_groupby_plan(const eiger_stats_t *keys, int32_t selector, const eiger_groupby_plan_t *forced,
                        eiger_groupby_plan_t *out);

@@ -355,8 +355,8 @@ def groupby(keys, vals, plan: Optional[GroupByPlanT] = None, capacity: Optional[
     """eiger_groupby: groups of `keys` with counts and sums of the value columns.
     Without a plan, the keys' statistics are computed and the rule planner picks
     one. A plan whose table turns out too small (the estimate was low) is run
-    again with a table of twice the rows; a result above `capacity` is run again
-    at its exact size."""
+    again with eight times the slots (on a copy of the plan); a result above
+    `capacity` is run again at its exact size."""
     import torch
     if plan is None:
         plan = groupby_plan(stats(keys, stream))
@@ -380,14 +380,12 @@ def groupby(keys, vals, plan: Optional[GroupByPlanT] = None, capacity: Optional[
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
         return rc, ok, oc, osum
 
+    plan = GroupByPlanT.from_buffer_copy(plan)
     if capacity is None:
         capacity = min(keys.numel(), int(plan.predicted_groups * 1.25) + 1024)
     rc, ok, oc, osum = run(plan, capacity)
-    if rc == EIGER_ERR_TOO_LARGE:
-        slots = 1024
-        while slots < 2 * keys.numel() + 1:
-            slots <<= 1
-        plan.slots = slots
+    while rc == EIGER_ERR_TOO_LARGE and plan.slots < 2 * keys.numel() + 1:
+        plan.slots *= 8
         rc, ok, oc, osum = run(plan, capacity)
     if rc == EIGER_ERR_CAPACITY:
         rc, ok, oc, osum = run(plan, groups.value)

@@ -36,7 +36,12 @@ constexpr uint32_t kGLds = 2048;            // LDS table slots (power of two)
 constexpr uint32_t kGLdsOpen = kGLds / 2;   // new groups an LDS table accepts
 constexpr int kGMaxVals = 2;
 constexpr uint32_t kGChunk = 1u << 16;      // rows per workgroup chunk (HASH)
-constexpr double kGbHashMaxGroups = 1 << 18;  // rule: HASH up to this many estimated groups
+constexpr int kGBatch = 8;                  // rows a thread loads before aggregating them
+constexpr uint64_t kGMaxProbe = 4096;       // longest walk in the global table
+// rule: HASH while the estimated groups fit one LDS table (beyond it, rows that
+// miss the LDS table cost global atomics per row, and PARTITION measured faster
+// from 2^14 groups up at 2^28 rows)
+constexpr double kGbHashMaxGroups = kGLdsOpen;
 constexpr double kGbGroupsPerPartition = 512.0;
 
 struct GbGlobal {
@@ -48,10 +53,14 @@ struct GbGlobal {
   uint32_t *overflow;
 };
 
+// Value columns as 32-bit words: lo and hi word arrays (for a 4-byte column hi
+// points at lo, so every load is unconditional), the word stride, and which
+// columns are 8 bytes wide.
 struct GbVals {
   const uint32_t *lo[kGMaxVals];
-  const uint32_t *hi[kGMaxVals];  // null: 4-byte column (sign-extended)
+  const uint32_t *hi[kGMaxVals];
   uint32_t stride[kGMaxVals];
+  uint32_t wide[kGMaxVals];
   int n;
 };
 
@@ -61,20 +70,24 @@ struct GbLds {
   unsigned long long sum[kGMaxVals][kGLds];
   uint32_t used;
   uint32_t spilled;
+  unsigned long long scan[kGNT / 64 + 1];
 };
 
-__device__ __forceinline__ uint64_t val_at(const GbVals &v, int c, uint64_t i) {
-  const uint64_t at = i * v.stride[c];
-  const uint32_t lo = v.lo[c][at];
-  if (v.hi[c]) return (uint64_t(v.hi[c][at]) << 32) | lo;
-  return static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(lo)));
+// A value from its two loaded words: 64-bit, or the low word sign-extended.
+__device__ __forceinline__ uint64_t combine(const GbVals &v, int c, uint32_t lo, uint32_t hi) {
+  return v.wide[c] ? (uint64_t(hi) << 32) | lo
+                   : static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(lo)));
 }
 
 // Slot of key k in the global table, claiming an empty one if needed; -1 when
 // the whole table was walked (more groups than slots: *overflow is set).
 __device__ __forceinline__ int64_t global_slot(const GbGlobal &t, unsigned long long k) {
   uint64_t s = fmix64(k) & t.mask;
-  for (uint64_t step = 0; step <= t.mask; ++step) {
+  // a table at most half full never needs a walk this long; stopping here keeps
+  // an overfull table (a far too low estimate) from costing a whole-table walk
+  // per row before the caller plans again with more slots
+  const uint64_t limit = t.mask < kGMaxProbe ? t.mask + 1 : kGMaxProbe;
+  for (uint64_t step = 0; step < limit; ++step) {
     // a slot changes once, from the sentinel to a key: any other value read is final
     const unsigned long long cur = __atomic_load_n(&t.key[s], __ATOMIC_RELAXED);
     if (cur == k) return static_cast<int64_t>(s);
@@ -104,9 +117,15 @@ __device__ __forceinline__ int lds_slot(GbLds &L, unsigned long long k, unsigned
     const unsigned long long cur = L.key[s];
     if (cur == k) return static_cast<int>(s);
     if (cur == sentinel) {
-      if (atomicAdd(&L.used, 1u) >= kGLdsOpen) return -1;  // closed for new groups
+      // closed for new groups once kGLdsOpen were claimed; claims racing with the
+      // last one can add at most one per thread of the workgroup
+      if (__atomic_load_n(&L.used, __ATOMIC_RELAXED) >= kGLdsOpen) return -1;
       const unsigned long long old = atomicCAS(&L.key[s], sentinel, k);
-      if (old == sentinel || old == k) return static_cast<int>(s);
+      if (old == sentinel) {
+        atomicAdd(&L.used, 1u);
+        return static_cast<int>(s);
+      }
+      if (old == k) return static_cast<int>(s);
     }
     s = (s + 1) & (kGLds - 1);
   }
@@ -126,21 +145,100 @@ __device__ __forceinline__ void lds_clear(GbLds &L, unsigned long long sentinel,
   __syncthreads();
 }
 
+// One row's contribution to the LDS table (or, when it is closed, to the global one).
+__device__ __forceinline__ void lds_add(GbLds &L, const GbGlobal &g, unsigned long long k, unsigned long long c,
+                                        const unsigned long long *sv, int nv) {
+  const int s = lds_slot(L, k, g.sentinel);
+  if (s >= 0) {
+    atomicAdd(&L.cnt[s], c);
+    for (int v = 0; v < nv; ++v) atomicAdd(&L.sum[v][s], sv[v]);
+  } else {
+    L.spilled = 1;
+    global_add(g, k, c, sv, nv);
+  }
+}
+
+// Groups a thread keeps in registers before its rows reach the LDS table: with
+// a handful of groups every row of a workgroup would otherwise hit the same few
+// LDS words, and same-address LDS atomics serialize.
+constexpr int kGRegGroups = 4;
+
 // Aggregate rows [lo, hi) into the LDS table (rows that do not fit go global).
-template <typename K>
+// kReg: first into per-thread register groups (HASH, few groups).
+template <typename K, bool kReg>
 __device__ __forceinline__ void aggregate_rows(GbLds &L, const GbGlobal &g, const K *__restrict__ keys,
                                                const GbVals &vals, uint64_t lo, uint64_t hi) {
-  for (uint64_t i = lo + threadIdx.x; i < hi; i += kGNT) {
-    const unsigned long long k = static_cast<unsigned long long>(sext(keys[i]));
-    unsigned long long sv[kGMaxVals];
-    for (int v = 0; v < vals.n; ++v) sv[v] = val_at(vals, v, i);
-    const int s = lds_slot(L, k, g.sentinel);
-    if (s >= 0) {
-      atomicAdd(&L.cnt[s], 1ull);
-      for (int v = 0; v < vals.n; ++v) atomicAdd(&L.sum[v][s], sv[v]);
-    } else {
-      L.spilled = 1;
-      global_add(g, k, 1ull, sv, vals.n);
+  unsigned long long rk[kGRegGroups], rc[kGRegGroups], rs[kGMaxVals][kGRegGroups];
+#pragma unroll
+  for (int j = 0; j < kGRegGroups; ++j) {
+    rk[j] = g.sentinel;
+    rc[j] = 0;
+#pragma unroll
+    for (int v = 0; v < kGMaxVals; ++v) rs[v][j] = 0;
+  }
+  // kGBatch rows per thread are loaded before any is aggregated, so each
+  // thread keeps several loads in flight; loaded words are only combined
+  // (sign extension, 64-bit values) after the whole batch was issued
+  constexpr uint64_t step = uint64_t(kGNT) * kGBatch;
+  for (uint64_t base = lo; base < hi; base += step) {
+    K rk_[kGBatch];
+    uint32_t wlo[kGBatch][kGMaxVals], whi[kGBatch][kGMaxVals];
+#pragma unroll
+    for (int b = 0; b < kGBatch; ++b) {
+      const uint64_t i = base + uint64_t(b) * kGNT + threadIdx.x;
+      if (i < hi) {
+        rk_[b] = keys[i];
+#pragma unroll
+        for (int v = 0; v < kGMaxVals; ++v) {
+          if (v < vals.n) {
+            const uint64_t at = i * vals.stride[v];
+            wlo[b][v] = vals.lo[v][at];
+            whi[b][v] = vals.hi[v][at];
+          }
+        }
+      }
+    }
+    unsigned long long bk[kGBatch], bv[kGBatch][kGMaxVals];
+#pragma unroll
+    for (int b = 0; b < kGBatch; ++b) {
+      const bool in = base + uint64_t(b) * kGNT + threadIdx.x < hi;
+      bk[b] = in ? static_cast<unsigned long long>(sext(rk_[b])) : g.sentinel;
+#pragma unroll
+      for (int v = 0; v < kGMaxVals; ++v)
+        bv[b][v] = v < vals.n && in ? combine(vals, v, wlo[b][v], whi[b][v]) : 0ull;
+    }
+#pragma unroll
+    for (int b = 0; b < kGBatch; ++b) {
+      const unsigned long long k = bk[b];
+      if (k == g.sentinel) continue;  // past the end (no key equals the sentinel)
+      const unsigned long long *sv = bv[b];
+      if (kReg) {
+        bool done = false;
+#pragma unroll
+        for (int j = 0; j < kGRegGroups; ++j) {
+          // a free register group takes the key if no earlier one holds it
+          if (!done && (rk[j] == k || rk[j] == g.sentinel)) {
+            rk[j] = k;
+            rc[j] += 1;
+#pragma unroll
+            for (int v = 0; v < kGMaxVals; ++v) rs[v][j] += sv[v];
+            done = true;
+          }
+        }
+        if (done) continue;
+      }
+      lds_add(L, g, k, 1ull, sv, vals.n);
+    }
+  }
+  if (kReg) {
+#pragma unroll
+    for (int j = 0; j < kGRegGroups; ++j) {
+      if (rk[j] != g.sentinel) {
+        unsigned long long sv[kGMaxVals];
+#pragma unroll
+        for (int v = 0; v < kGMaxVals; ++v) sv[v] = rs[v][j];
+        lds_add(L, g, rk[j], rc[j], sv, vals.n);
+      }
     }
   }
   __syncthreads();
@@ -177,27 +275,42 @@ __device__ __forceinline__ void put_group(const GbOut &o, uint64_t pos, unsigned
   for (int v = 0; v < nv; ++v) o.sum[v][pos] = sv[v];
 }
 
-// Emit the occupied slots of one table range [lo, hi) of (key, cnt, sums) arrays,
-// one output reservation per wave.
+// Emit the occupied slots of one table range [lo, hi) of (key, cnt, sums)
+// arrays. The whole workgroup walks the range in rounds of kGEmitPer slots per
+// thread (each thread a contiguous run), and each round reserves its output
+// with ONE atomic: a device-wide counter that every wave hit separately cost
+// more than the rest of a group-by with millions of groups. Uniform across
+// the workgroup (contains barriers); `scan` holds kGNT / 64 + 1 words of LDS.
+constexpr int kGEmitPer = 8;
 __device__ __forceinline__ void emit_range(const unsigned long long *key, const unsigned long long *cnt,
                                            const unsigned long long *sum0, const unsigned long long *sum1,
                                            uint64_t lo, uint64_t hi, unsigned long long sentinel, int nv,
-                                           const GbOut &o) {
-  const uint32_t lane = __lane_id();
-  const uint64_t wlo = lo + (threadIdx.x / 64) * 64, wstep = kGNT;
-  for (uint64_t base = wlo; base < hi; base += wstep) {
-    const uint64_t i = base + lane;
-    const bool live = i < hi && key[i] != sentinel;
-    const uint64_t m = __ballot(live);
-    if (m == 0) continue;
-    unsigned long long at = 0;
-    if (lane == 0) at = atomicAdd(o.cursor, static_cast<unsigned long long>(__popcll(m)));
-    at = __shfl(at, 0, 64);
-    if (live) {
+                                           const GbOut &o, unsigned long long *scan) {
+  constexpr uint64_t round = uint64_t(kGNT) * kGEmitPer;
+  for (uint64_t base = lo; base < hi; base += round) {
+    const uint64_t mine = base + uint64_t(threadIdx.x) * kGEmitPer;
+    uint32_t live = 0;
+#pragma unroll
+    for (int j = 0; j < kGEmitPer; ++j) {
+      const uint64_t i = mine + j;
+      if (i < hi && key[i] != sentinel) live |= 1u << j;
+    }
+    unsigned long long total;
+    const unsigned long long off =
+        block_exclusive_scan<kGNT, unsigned long long>(static_cast<unsigned long long>(__popc(live)), scan, &total);
+    if (total == 0) continue;
+    if (threadIdx.x == 0) scan[kGNT / 64] = atomicAdd(o.cursor, total);
+    __syncthreads();
+    unsigned long long at = scan[kGNT / 64] + off;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kGEmitPer; ++j) {
+      if (!((live >> j) & 1u)) continue;
+      const uint64_t i = mine + j;
       unsigned long long sv[kGMaxVals] = {0, 0};
       if (nv > 0) sv[0] = sum0[i];
       if (nv > 1) sv[1] = sum1[i];
-      put_group(o, at + lane_prefix(m), key[i], cnt[i], sv, nv);
+      put_group(o, at++, key[i], cnt[i], sv, nv);
     }
   }
 }
@@ -217,28 +330,32 @@ __global__ void __launch_bounds__(kGNT) k_gb_hash(const K *__restrict__ keys, ui
   __shared__ GbLds L;
   for (uint64_t lo = uint64_t(blockIdx.x) * kGChunk; lo < n; lo += uint64_t(gridDim.x) * kGChunk) {
     lds_clear(L, g.sentinel, vals.n);
-    aggregate_rows<K>(L, g, keys, vals, lo, min(n, lo + kGChunk));
+    aggregate_rows<K, true>(L, g, keys, vals, lo, min(n, lo + kGChunk));
     lds_merge(L, g, vals.n);
     __syncthreads();
   }
 }
 
-// PARTITION: one partition per work item; groups written out directly unless
-// the partition spilled, in which case they are merged into the global table.
+// PARTITION: work item = one of the S equal slices of a partition (S = 1 when
+// partitions are small). A whole partition that did not spill writes its groups
+// out directly; slices and spilled partitions merge into the global table.
 template <typename K>
 __global__ void __launch_bounds__(kGNT)
-    k_gb_partition(const K *__restrict__ keys, GbVals vals, const uint32_t *__restrict__ off, uint32_t F, GbGlobal g,
-                   GbOut o) {
+    k_gb_partition(const K *__restrict__ keys, GbVals vals, const uint32_t *__restrict__ off, uint32_t F, uint32_t S,
+                   GbGlobal g, GbOut o) {
   __shared__ GbLds L;
-  for (uint32_t p = blockIdx.x; p < F; p += gridDim.x) {
-    const uint32_t lo = off[p], hi = off[p + 1];
+  const uint64_t items = uint64_t(F) * S;
+  for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const uint32_t p = static_cast<uint32_t>(it / S), sl = static_cast<uint32_t>(it % S);
+    const uint64_t plo = off[p], len = off[p + 1] - plo;
+    const uint64_t lo = plo + len * sl / S, hi = plo + len * (sl + 1) / S;
     if (lo == hi) continue;
     lds_clear(L, g.sentinel, vals.n);
-    aggregate_rows<K>(L, g, keys, vals, lo, hi);
-    if (L.spilled) {
+    aggregate_rows<K, false>(L, g, keys, vals, lo, hi);
+    if (L.spilled || S > 1) {
       lds_merge(L, g, vals.n);
     } else {
-      emit_range(L.key, L.cnt, L.sum[0], L.sum[1], 0, kGLds, g.sentinel, vals.n, o);
+      emit_range(L.key, L.cnt, L.sum[0], L.sum[1], 0, kGLds, g.sentinel, vals.n, o, L.scan);
     }
     __syncthreads();
   }
@@ -249,12 +366,24 @@ __global__ void __launch_bounds__(kGNT) k_gb_emit(GbGlobal g, int nv, GbOut o) {
   const uint64_t slots = g.mask + 1;
   const uint64_t per = (slots + gridDim.x - 1) / gridDim.x;
   const uint64_t lo = uint64_t(blockIdx.x) * per, hi = min(slots, lo + per);
-  emit_range(g.key, g.cnt, g.sum[0], g.sum[1], lo, hi, g.sentinel, nv, o);
+  __shared__ unsigned long long scan[kGNT / 64 + 1];
+  emit_range(g.key, g.cnt, g.sum[0], g.sum[1], lo, hi, g.sentinel, nv, o, scan);
 }
 
 int gb_sentinel(const eiger_groupby_plan_t &p, unsigned long long *out) {
   *out = static_cast<unsigned long long>(p.sentinel);
   return EIGER_OK;
+}
+
+// Slices per partition: few partitions (few groups) are cut into slices so the
+// grid still has about four work items per CU of the 256; slices keep at least
+// 2^14 rows. With more than one slice every group reaches the global table.
+constexpr uint64_t kGTargetItems = 1024;
+uint32_t gb_slices(uint64_t n, int bits) {
+  const uint64_t F = uint64_t(1) << bits;
+  uint32_t S = 1;
+  while (uint64_t(S) * F < kGTargetItems && n / (uint64_t(S) * 2 * F) >= (uint64_t(1) << 14)) S <<= 1;
+  return S;
 }
 
 uint64_t gb_slots(double groups) {
@@ -289,7 +418,8 @@ GbVals gb_vals(const eiger_column *vals, int32_t nv) {
     const uint32_t *base = static_cast<const uint32_t *>(vals[c].data);
     const bool wide = vals[c].dtype == EIGER_INT64;
     v.lo[c] = base;
-    v.hi[c] = wide && base ? base + 1 : nullptr;
+    v.hi[c] = wide && base ? base + 1 : base;
+    v.wide[c] = wide ? 1u : 0u;
     v.stride[c] = wide ? 2 : 1;
   }
   return v;
@@ -346,13 +476,16 @@ int gb_impl(const eiger_column &keys, const eiger_column *vals, int32_t nv, cons
     for (int32_t c = 0; c < nv; ++c) {
       const bool wide = vals[c].dtype == EIGER_INT64;
       v.lo[c] = part.words[w];
-      v.hi[c] = wide ? part.words[w + 1] : nullptr;
+      v.hi[c] = wide ? part.words[w + 1] : part.words[w];
+      v.wide[c] = wide ? 1u : 0u;
       v.stride[c] = 1;
       w += wide ? 2 : 1;
     }
     const uint32_t F = 1u << plan.radix_bits;
-    EIGER_LAUNCH("groupby_partition", k_gb_partition<K>, dim3(std::min<uint32_t>(F, cus * 2)), dim3(kGNT), 0, s,
-                 static_cast<const K *>(part.keys), v, part.off, F, g, o);
+    const uint32_t S = gb_slices(n, plan.radix_bits);
+    EIGER_LAUNCH("groupby_partition", k_gb_partition<K>,
+                 dim3(static_cast<unsigned>(std::min<uint64_t>(uint64_t(F) * S, cus * 2))), dim3(kGNT), 0, s,
+                 static_cast<const K *>(part.keys), v, part.off, F, S, g, o);
   }
   EIGER_LAUNCH("groupby_emit", k_gb_emit, dim3(static_cast<unsigned>(std::min<uint64_t>(
                                               (plan.slots + 4095) / 4096, cus * 4))),
@@ -433,9 +566,10 @@ extern "C" int eiger_groupby_plan(const eiger_stats_t *keys, int32_t selector, c
     while (bits < 18 && est / std::ldexp(1.0, bits) > kGbGroupsPerPartition) ++bits;
     p.radix_bits = bits;
   }
-  // the global table: NDV-sized (twice the estimate); the partitioned variant
-  // only spills into it
-  p.slots = static_cast<int64_t>(gb_slots(p.variant == EIGER_GB_HASH ? est : est / 8.0));
+  // the global table: NDV-sized (twice the estimate) when every group reaches
+  // it (HASH, or sliced partitions); unsliced partitions only spill into it
+  const bool all_global = p.variant == EIGER_GB_HASH || gb_slices(static_cast<uint64_t>(keys->n), p.radix_bits) > 1;
+  p.slots = static_cast<int64_t>(gb_slots(all_global ? est : est / 8.0));
   *out = p;
   return EIGER_OK;
 }

@@ -28,8 +28,9 @@ def forced(keys, variant, bits=0):
     return eg.groupby_plan(eg.stats(keys), eg.SEL_FORCED, eg.make_groupby_plan(variant, bits))
 
 
-VARIANTS = [("hash", eg.GB_HASH, 0), ("part4", eg.GB_PARTITION, 4), ("part8", eg.GB_PARTITION, 8),
-            ("part12p2", eg.GB_PARTITION, 12)]
+# part2: 4 partitions of ~250,000 rows, each aggregated in 4 slices merged globally
+VARIANTS = [("hash", eg.GB_HASH, 0), ("part2", eg.GB_PARTITION, 2), ("part4", eg.GB_PARTITION, 4),
+            ("part8", eg.GB_PARTITION, 8), ("part12p2", eg.GB_PARTITION, 12)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=[v[0] for v in VARIANTS])
@@ -50,11 +51,11 @@ def test_groupby_int64_keys_and_values(gpu, variant):
 
 
 def test_groupby_rule_follows_the_estimate(gpu):
-    small, sv = synth.groupby_input(seed=1, n=2_000_000, groups=3000, device=gpu)
+    small, sv = synth.groupby_input(seed=1, n=2_000_000, groups=600, device=gpu)
     big, bv = synth.groupby_input(seed=2, n=2_000_000, groups=1_500_000, device=gpu)
     ps, pb = eg.groupby_plan(eg.stats(small)), eg.groupby_plan(eg.stats(big))
     assert ps.variant == eg.GB_HASH and pb.variant == eg.GB_PARTITION
-    assert abs(ps.predicted_groups - 3000) < 3000 * 0.05
+    assert abs(ps.predicted_groups - 600) < 600 * 0.05
     check(small, sv, eg.groupby(small, sv, ps))
     check(big, bv, eg.groupby(big, bv, pb))
 
