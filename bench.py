@@ -294,6 +294,150 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
                          f"{len(waves)} waves that fit HBM")}
 
 
+
+def bench_groupby(n_log2=28, reps=3, seed=42, groups_log2=(2, 6, 10, 14, 16, 18, 20, 22, 24, 26)):
+    """Group-by at the paper's microbenchmark shape (Section 5.3: 2^28 rows, two
+    aggregated columns, g groups): HASH, PARTITION and the HLL-guided choice
+    ("auto", which includes the statistics pass) for 4-byte and 8-byte keys and
+    values. Each cell is the minimum of `reps` timed runs after one warm-up."""
+    import torch
+    import paper_2607_04489_amd as eg
+    import synth
+    dev = torch.device("cuda:0")
+    n = 1 << n_log2
+    rows = []
+    for dt in (torch.int32, torch.int64):
+        name = "int32" if dt == torch.int32 else "int64"
+        ws_stats = torch.empty(eg.lib().eiger_stats_workspace_size(n, eg.column(torch.empty(0, dtype=dt)).dtype),
+                               dtype=torch.uint8, device=dev)
+        for lg in groups_log2:
+            g = 1 << lg
+            keys, vals = synth.groupby_input(seed, n, g, key_dtype=dt, n_vals=2, val_dtype=dt, device=dev)
+            torch.cuda.synchronize()
+            cap = min(n, int(g * 1.25) + 1024)
+            res, cell = {}, {"key": name, "groups_log2": lg}
+            st0 = eg.stats(keys, workspace=ws_stats)
+            fixed = {k: eg.groupby_plan(st0, eg.SEL_FORCED, eg.make_groupby_plan(v))
+                     for k, v in (("hash", eg.GB_HASH), ("partition", eg.GB_PARTITION))}
+
+            def run(kind):
+                if kind == "auto":  # statistics and plan are part of the timed work
+                    return eg.groupby(keys, vals, eg.groupby_plan(eg.stats(keys, workspace=ws_stats)), capacity=cap)
+                return eg.groupby(keys, vals, fixed[kind], capacity=cap)
+
+            for kind in ("hash", "partition", "auto"):
+                best = None
+                for r in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    out = run(kind)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3
+                    if r > 0:
+                        best = ms if best is None else min(best, ms)
+                res[kind] = out
+                cell[kind + "_ms"] = round(best, 3)
+                if kind == "auto":
+                    cell["auto_choice"] = eg.GB_NAMES[out.plan.variant]
+                    cell["auto_bits"] = int(out.plan.radix_bits)
+                    cell["hll_groups"] = int(out.plan.predicted_groups)
+                elif kind == "partition":
+                    cell["partition_bits"] = int(out.plan.radix_bits)
+            a, b, c = (res[k] for k in ("hash", "partition", "auto"))
+            cell["groups"] = a.groups
+            cell["agree"] = bool(a.groups == b.groups == c.groups
+                                 and int(a.counts.sum()) == int(b.counts.sum()) == n
+                                 and all(int(x.sum()) == int(y.sum()) for x, y in zip(a.sums, b.sums)))
+            best_fixed = min(cell["hash_ms"], cell["partition_ms"])
+            cell["auto_vs_best_fixed"] = round(best_fixed / cell["auto_ms"], 3)
+            log(json.dumps(cell))
+            rows.append(cell)
+            del keys, vals, res, a, b, c
+            torch.cuda.empty_cache()
+    return {"metric": "group-by rows/s (2^28 rows, 2 sums): hash vs partition vs HLL-guided auto",
+            "rows": n, "unit": "ms per group-by (statistics included for auto)", "cells": rows,
+            "workload": "2^28 rows, keys uniform over g distinct values spread over the key type, two value "
+                        "columns of the key's width uniform over the full range"}
+
+
+# Table 4 of the paper (GH200, 2^28 rows, 4 int32 keys): the SKF + radix sort
+# breakdown, for context only (another machine).
+PAPER_SKF_SORT_GH200_MS = {"radix_sort": 12.224, "dictionary_encoding": 6.936, "fusing_keys": 3.393,
+                           "hll": 1.061}
+
+
+def bench_skf_sort(n_log2=28, reps=3, seed=42, configs=((4, "int32"), (2, "int32"), (4, "int64"), (2, "int64"))):
+    """Multi-key sort through smart key fusion at the paper's sorting shape
+    (Section 5.6: 2^28 rows, 2 or 4 keys of int32 or int64; half of the keys
+    narrow -- frame of reference --, half sparse with few distinct values --
+    dictionary). One step = statistics (min/max/HLL) of every key, the fusion
+    plan, the dictionary encodings, the fusion kernel and the radix sort of the
+    fused keys with the row ids (the sorting permutation). Per-kernel times come
+    from the library's HIP-event timing on the launch stream."""
+    import torch
+    import paper_2607_04489_amd as eg
+    import synth
+    dev = torch.device("cuda:0")
+    n = 1 << n_log2
+    out = []
+    for n_keys, dt_name in configs:
+        dt = torch.int32 if dt_name == "int32" else torch.int64
+        cols = synth.multikey_table(seed, n, n_keys, dt, narrow_bits=8, sparse_ndv=256, device=dev)
+        torch.cuda.synchronize()
+
+        def step():
+            st = [eg.stats(c) for c in cols]
+            return eg.sort_multikey(cols, plan=eg.skf_plan(st))
+
+        perm, _, fin = step()
+        torch.cuda.synchronize()
+        # the result is a permutation and orders the rows by the key tuples
+        ok = bool(torch.bincount(perm.long(), minlength=n).eq(1).all())
+        srt = [c[perm.long()] for c in cols]
+        diff = torch.zeros(n - 1, dtype=torch.int8, device=dev)   # 1: decided greater, -1: decided smaller
+        for c in srt:
+            undecided = diff == 0
+            diff = torch.where(undecided & (c[1:] > c[:-1]), torch.ones_like(diff), diff)
+            diff = torch.where(undecided & (c[1:] < c[:-1]), -torch.ones_like(diff), diff)
+        ok = ok and bool((diff >= 0).all())
+        del srt, diff
+        best, prof = None, None
+        for r in range(reps):
+            torch.cuda.synchronize()
+            eg.profile_enable(True)
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            table = eg.profile_read()
+            eg.profile_enable(False)
+            if best is None or ms < best:
+                best, prof = ms, table
+        kb = 4 if fin.fused_bytes == 4 else 8
+        scat = prof.get("sort_scatter", (0, 0.0))
+        passes = max(1, (int(fin.total_bits) + 7) // 8)
+        # sort_scatter algorithmic bytes of the row sort's passes: read key + value,
+        # write key + value (the first pass generates the row ids instead of reading
+        # them); the few small launches that sort the dictionaries' distinct values
+        # are inside the measured time
+        alg = n * (2 * kb + 8) * passes - n * 4
+        cell = {"keys": n_keys, "dtype": dt_name, "rows": n, "ms": round(best, 3),
+                "rows_per_s": n / (best * 1e-3), "fused_bytes": int(fin.fused_bytes),
+                "total_bits": int(fin.total_bits), "codes": [k["code"] for k in fin.describe()["keys"]],
+                "sorted_ok": ok,
+                "kernels_ms": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda x: -x[1][1])},
+                "sort_scatter": {"launches": scat[0], "ms": round(scat[1], 3),
+                                 "alg_GBps": round(alg / (scat[1] * 1e-3) / 1e9, 1) if scat[1] else None}}
+        log(json.dumps(cell))
+        out.append(cell)
+        del cols
+        torch.cuda.empty_cache()
+    return {"metric": "multi-key sort rows/s via smart key fusion + radix sort", "unit": "rows/s",
+            "cells": out, "paper_gh200_4xi32_ms": PAPER_SKF_SORT_GH200_MS,
+            "workload": "2^28 rows; even keys narrow (base + U[0, 2^8)), odd keys one of 256 values spread "
+                        "over the type's range; all ascending"}
+
+
 def host_cores():
     """Host CPUs this process may run on (the GPU machine grants 16)."""
     return max(1, min(16, len(os.sched_getaffinity(0))))
@@ -397,6 +541,12 @@ def main():
     if args.workload == "batched":
         import torch  # noqa: F401
         print(json.dumps(bench_batched(autotune=args.autotune)), flush=True)
+        return
+    if args.workload == "groupby":
+        print(json.dumps(bench_groupby(reps=max(1, args.steps))), flush=True)
+        return
+    if args.workload == "skf_sort":
+        print(json.dumps(bench_skf_sort(reps=max(1, args.steps))), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "

@@ -295,6 +295,118 @@ int eiger_groupby(eiger_column keys, const eiger_column *vals, int32_t n_vals, c
                   void *out_keys, int64_t *out_counts, int64_t *const *out_sums, int64_t out_capacity,
                   int64_t *out_groups, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- sorting and smart key fusion (Sections 3.6 and 4.3, Algorithm 1) ----------
+ * A sort on one numeric key is a radix sort; several numeric keys are first
+ * fused into one 4- or 8-byte key (smart key fusion) and then radix-sorted. The
+ * same fused key turns a join on several key columns into a single-key join.
+ */
+
+/* Workspace bytes for eiger_sort_pairs with these arguments. */
+int eiger_sort_pairs_workspace_size(int32_t key_bytes, int64_t n, int32_t key_bits, size_t *bytes);
+
+/*
+ * Stable LSD radix sort of n (key, value) pairs, ascending by the unsigned value
+ * of the key's low key_bits bits (bits above are ignored, so pass keys below
+ * 2^key_bits). key_bytes 4 or 8 (uint32 / uint64 keys); key_bits 0..8*key_bytes
+ * sets the number of passes (ceil(key_bits / 8)). keys_in, vals_in, keys_out,
+ * vals_out: DEVICE arrays of n entries; vals_in == NULL sorts the row ids
+ * 0..n-1 along (vals_out is then the stable sorting permutation). Outputs must
+ * not alias inputs. Does not synchronize `stream`.
+ */
+int eiger_sort_pairs(int32_t key_bytes, const void *keys_in, const uint32_t *vals_in, int64_t n, int32_t key_bits,
+                     void *keys_out, uint32_t *vals_out, void *ws, size_t ws_bytes, void *stream);
+
+#define EIGER_SKF_MAX_KEYS 8
+#define EIGER_SKF_FOR_MAX_BITS 16        /* default: keys whose range fits 16 bits take frame of reference */
+#define EIGER_SKF_DICT_MAX_NDV (1 << 20) /* default: keys of up to 2^20 distinct values take the dictionary */
+typedef enum { EIGER_SKF_FOR = 0, EIGER_SKF_DICT = 1 } eiger_skf_code;
+
+typedef struct {
+    int32_t code;       /* eiger_skf_code */
+    int32_t bits;       /* width of the key's code inside the fused key */
+    int32_t shift;      /* position of the code's lowest bit in the fused key */
+    int32_t descending; /* 1: the key sorts descending (its code is complemented within its width) */
+    int64_t base;       /* FOR: the minimum subtracted from every key */
+    int64_t ndv;        /* DICT: distinct estimate in a plan, exact count after eiger_skf_fuse */
+    int64_t slots;      /* DICT: slots of the encoding's hash table (power of two) */
+    int32_t dtype;      /* EIGER_INT32 / EIGER_INT64 */
+    int32_t range_bits; /* bit width of max - min (DICT: the sort width of the distinct values) */
+} eiger_skf_key_t;
+
+typedef struct {
+    int32_t n_keys;
+    int32_t total_bits;  /* sum of the key widths */
+    int32_t fused_bytes; /* 4 or 8; 0: the codes need more than 64 bits and cannot be fused */
+    int32_t reserved;
+    eiger_skf_key_t key[EIGER_SKF_MAX_KEYS];
+} eiger_skf_plan_t;
+
+/*
+ * Smart key fusion plan (Section 4.3) from per-key statistics (HOST arrays of
+ * n_keys entries; stats from eiger_stats). Per key, in order: a range max - min
+ * of at most for_max_bits bits takes frame-of-reference encoding at that width;
+ * otherwise an HLL distinct estimate of at most dict_max_ndv takes the
+ * order-preserving dictionary (its width is set from the exact count when
+ * eiger_skf_fuse encodes it; the plan holds the estimate's width); otherwise the
+ * key keeps its full frame-of-reference width. The first key takes the most
+ * significant bits. descending may be NULL (all ascending). Host only.
+ */
+int eiger_skf_plan(const eiger_stats_t *stats, const int32_t *descending, int32_t n_keys, int32_t for_max_bits,
+                   int64_t dict_max_ndv, eiger_skf_plan_t *out);
+
+/* The same plan for a join on n_keys columns of two relations: each key's
+ * frame of reference spans both sides' range, its dictionary covers both
+ * sides' values (the estimate is the sum of the two estimates), all ascending. */
+int eiger_skf_plan_join(const eiger_stats_t *build_stats, const eiger_stats_t *probe_stats, int32_t n_keys,
+                        int32_t for_max_bits, int64_t dict_max_ndv, eiger_skf_plan_t *out);
+
+/* Workspace bytes for eiger_skf_fuse / eiger_sort_multikey with this plan and these row counts. */
+int eiger_skf_workspace_size(const eiger_skf_plan_t *plan, int64_t n_a, int64_t n_b, int32_t sort, size_t *bytes);
+
+/*
+ * Fuse the key columns of one relation (keys_a, n_keys DEVICE columns of equal
+ * length) or of two (keys_b, same key dtypes; NULL for one) into one key per row:
+ * dictionary keys are encoded over all rows of both relations together
+ * (Algorithm 1: hash-table group ids with a leader per value, the distinct values
+ * retrieved, sorted, and their positions scattered to the groups and gathered
+ * by every row), then each row's codes are shifted into place (Section 4.3).
+ * out_a / out_b: DEVICE, 8 bytes per row of capacity; they receive uint32 keys
+ * when out_plan->fused_bytes == 4, uint64 keys when 8. *out_plan (HOST) is the
+ * plan with each dictionary key's exact count and width. Comparing fused keys as
+ * unsigned integers orders rows lexicographically by the keys (ascending or
+ * descending per key); equal fused keys mean equal key tuples.
+ * EIGER_ERR_UNSUPPORTED when the exact widths need more than 64 bits (*out_plan
+ * is still set); EIGER_ERR_TOO_LARGE when a key has more distinct values than
+ * half its table's slots (plan again with more slots). Synchronizes `stream`.
+ */
+int eiger_skf_fuse(const eiger_column *keys_a, const eiger_column *keys_b, int32_t n_keys,
+                   const eiger_skf_plan_t *plan, void *out_a, void *out_b, eiger_skf_plan_t *out_plan, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/*
+ * Multi-key sort (Section 3.6, case 2): eiger_skf_fuse on one relation, then
+ * eiger_sort_pairs of the fused keys with the row ids. out_perm (DEVICE, n
+ * uint32): rows in sorted order (stable: equal key tuples keep their row order).
+ * out_sorted (DEVICE, 8 bytes per row of capacity, may be NULL): the sorted
+ * fused keys, 4 or 8 bytes each as out_plan->fused_bytes says. Synchronizes
+ * `stream`; errors as eiger_skf_fuse.
+ */
+int eiger_sort_multikey(const eiger_column *keys, int32_t n_keys, const eiger_skf_plan_t *plan, uint32_t *out_perm,
+                        void *out_sorted, eiger_skf_plan_t *out_plan, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Order-preserving dictionary encoding of one column (Algorithm 1): out_codes
+ * (DEVICE, n uint32) = the rank of each row's value among the column's distinct
+ * values; out_dict (DEVICE, key dtype, dict_capacity entries, may be NULL) = the
+ * distinct values ascending; *out_ndv (HOST) = their number. slots: hash-table
+ * slots (power of two >= 2); EIGER_ERR_TOO_LARGE when the column has more than
+ * slots / 2 distinct values, EIGER_ERR_CAPACITY when more than dict_capacity
+ * (with out_dict given). Synchronizes `stream`.
+ */
+int eiger_dict_encode_workspace_size(eiger_column col, int64_t slots, size_t *bytes);
+int eiger_dict_encode(eiger_column col, int64_t slots, uint32_t *out_codes, void *out_dict, int64_t dict_capacity,
+                      int64_t *out_ndv, void *ws, size_t ws_bytes, void *stream);
+
 /* Bytes of the fixed device scratch array behind eiger_join_noalloc (64 MiB). */
 #define EIGER_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 

@@ -8,6 +8,7 @@ library. Plain numpy, written from the paper:
   * skf_plan       -- smart key fusion: per key, frame-of-reference or dictionary
                       code and its bit width; fused key width (Section 4.3)
   * fuse           -- the fused 4- or 8-byte key of each row (Section 4.3)
+  * sort_pairs     -- the stable order of (key, row) pairs by a key's low bits
   * sort_multikey  -- rows ordered by several keys, each ascending or descending
                       (Section 3.6, cases 1 and 2)
   * join_multikey  -- the inner equi-join on several key columns (Section 4.3:
@@ -133,6 +134,20 @@ def fuse(cols, plan: SkfPlan, dict_codes=None) -> np.ndarray:
     return out.astype(np.uint32) if plan.fused_bytes == 4 else out
 
 
+def sort_pairs(keys, key_bits: int):
+    """Radix sort's result (Section 3.6, case 1): the keys ordered ascending by
+    the unsigned value of their low key_bits bits, and the stable permutation
+    that orders them (equal keys keep their input order, as every LSD radix pass
+    does). Plain definition: numpy's stable argsort of the masked keys. Returns
+    (masked keys sorted as uint64, permutation int64)."""
+    k = np.asarray(keys)
+    k = k.view(np.uint32 if k.dtype.itemsize == 4 else np.uint64).astype(np.uint64)
+    if key_bits < 64:
+        k = k & np.uint64((1 << key_bits) - 1)
+    perm = np.argsort(k, kind="stable")
+    return k[perm], perm
+
+
 def sort_multikey(cols, descending):
     """Rows ordered lexicographically by the key columns, each ascending or
     descending (Section 3.6). Plain definition: Python's sort of the key tuples,
@@ -172,4 +187,5 @@ def join_multikey(colsR, colsS, threads: int = 1) -> np.ndarray:
 
 
 __all__ = ["FOR", "DICT", "DEFAULT_FOR_MAX_BITS", "DEFAULT_DICT_MAX_NDV", "dict_encode", "bit_width",
-           "KeyCode", "SkfPlan", "skf_plan", "fuse", "sort_multikey", "join_multikey", "canonical_pairs"]
+           "KeyCode", "SkfPlan", "skf_plan", "fuse", "sort_pairs", "sort_multikey", "join_multikey",
+           "canonical_pairs"]

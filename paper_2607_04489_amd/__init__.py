@@ -91,6 +91,30 @@ class GroupByPlanT(ctypes.Structure):
 
 
 GB_HASH, GB_PARTITION = 0, 1
+
+
+class SkfKeyT(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("bits", ctypes.c_int32), ("shift", ctypes.c_int32),
+                ("descending", ctypes.c_int32), ("base", ctypes.c_int64), ("ndv", ctypes.c_int64),
+                ("slots", ctypes.c_int64), ("dtype", ctypes.c_int32), ("range_bits", ctypes.c_int32)]
+
+
+SKF_MAX_KEYS = 8
+SKF_FOR, SKF_DICT = 0, 1
+SKF_FOR_MAX_BITS = 16
+SKF_DICT_MAX_NDV = 1 << 20
+
+
+class SkfPlanT(ctypes.Structure):
+    _fields_ = [("n_keys", ctypes.c_int32), ("total_bits", ctypes.c_int32), ("fused_bytes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("key", SkfKeyT * SKF_MAX_KEYS)]
+
+    def describe(self) -> dict:
+        return {"total_bits": int(self.total_bits), "fused_bytes": int(self.fused_bytes),
+                "keys": [{"code": "dict" if k.code == SKF_DICT else "for", "bits": int(k.bits),
+                          "shift": int(k.shift), "descending": bool(k.descending), "base": int(k.base),
+                          "ndv": int(k.ndv), "slots": int(k.slots)}
+                         for k in self.key[: self.n_keys]]}
 GB_NAMES = {GB_HASH: "hash", GB_PARTITION: "partition"}
 
 
@@ -147,6 +171,25 @@ def lib():
         L.eiger_join_noalloc.argtypes = [Column, Column, Column, Column, ctypes.POINTER(PlanT), vp, vp, i64,
                                          ctypes.POINTER(i64), ctypes.POINTER(i64), vp]
         L.eiger_join_noalloc.restype = ctypes.c_int
+        psk = ctypes.POINTER(SkfPlanT)
+        L.eiger_sort_pairs_workspace_size.argtypes = [i32, i64, i32, ctypes.POINTER(sz)]
+        L.eiger_sort_pairs_workspace_size.restype = ctypes.c_int
+        L.eiger_sort_pairs.argtypes = [i32, vp, vp, i64, i32, vp, vp, vp, sz, vp]
+        L.eiger_sort_pairs.restype = ctypes.c_int
+        L.eiger_skf_plan.argtypes = [ctypes.POINTER(StatsT), vp, i32, i32, i64, psk]
+        L.eiger_skf_plan.restype = ctypes.c_int
+        L.eiger_skf_plan_join.argtypes = [ctypes.POINTER(StatsT), ctypes.POINTER(StatsT), i32, i32, i64, psk]
+        L.eiger_skf_plan_join.restype = ctypes.c_int
+        L.eiger_skf_workspace_size.argtypes = [psk, i64, i64, i32, ctypes.POINTER(sz)]
+        L.eiger_skf_workspace_size.restype = ctypes.c_int
+        L.eiger_skf_fuse.argtypes = [vp, vp, i32, psk, vp, vp, psk, vp, sz, vp]
+        L.eiger_skf_fuse.restype = ctypes.c_int
+        L.eiger_sort_multikey.argtypes = [vp, i32, psk, vp, vp, psk, vp, sz, vp]
+        L.eiger_sort_multikey.restype = ctypes.c_int
+        L.eiger_dict_encode_workspace_size.argtypes = [Column, i64, ctypes.POINTER(sz)]
+        L.eiger_dict_encode_workspace_size.restype = ctypes.c_int
+        L.eiger_dict_encode.argtypes = [Column, i64, vp, vp, i64, ctypes.POINTER(i64), vp, sz, vp]
+        L.eiger_dict_encode.restype = ctypes.c_int
         L.eiger_last_error.argtypes = []
         L.eiger_last_error.restype = ctypes.c_char_p
         L.eiger_version.restype = ctypes.c_int
@@ -392,6 +435,184 @@ def groupby(keys, vals, plan: Optional[GroupByPlanT] = None, capacity: Optional[
     _check(rc)
     g = groups.value
     return GroupByResult(ok[:g], oc[:g], [t[:g] for t in osum], g, plan)
+
+
+
+def sort_pairs(keys, key_bits: int, vals=None, stream=None, workspace=None):
+    """eiger_sort_pairs: stable LSD radix sort of (key, value) pairs by the low
+    key_bits bits of the key. keys: a device int32 or int64 tensor holding the
+    unsigned key bits; vals: int32 tensor (row ids 0..n-1 when None). Returns
+    (sorted keys, values in sorted order)."""
+    import torch
+    n = keys.numel()
+    kb = keys.element_size()
+    need = ctypes.c_size_t()
+    _check(lib().eiger_sort_pairs_workspace_size(kb, n, key_bits, ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value,
+                                                                                             keys.device)
+    ko = torch.empty_like(keys)
+    vo = torch.empty(n, dtype=torch.int32, device=keys.device)
+    _check(lib().eiger_sort_pairs(kb, ctypes.c_void_p(keys.data_ptr()),
+                                  ctypes.c_void_p(vals.data_ptr()) if vals is not None else None, n, key_bits,
+                                  ctypes.c_void_p(ko.data_ptr()), ctypes.c_void_p(vo.data_ptr()),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return ko, vo
+
+
+def _stats_array(items):
+    arr = (StatsT * len(items))()
+    for i, st in enumerate(items):
+        arr[i] = st.raw
+    return arr
+
+
+def skf_plan(key_stats, descending=None, for_max_bits: int = SKF_FOR_MAX_BITS,
+             dict_max_ndv: int = SKF_DICT_MAX_NDV) -> SkfPlanT:
+    """eiger_skf_plan: frame-of-reference or dictionary code per key from its statistics."""
+    out = SkfPlanT()
+    desc = (ctypes.c_int32 * len(key_stats))(*[int(bool(d)) for d in (descending or [0] * len(key_stats))])
+    _check(lib().eiger_skf_plan(_stats_array(key_stats), desc, len(key_stats), for_max_bits, dict_max_ndv,
+                                ctypes.byref(out)))
+    return out
+
+
+def skf_plan_join(build_stats, probe_stats, for_max_bits: int = SKF_FOR_MAX_BITS,
+                  dict_max_ndv: int = SKF_DICT_MAX_NDV) -> SkfPlanT:
+    """eiger_skf_plan_join: one fusion plan valid for both relations of a join."""
+    out = SkfPlanT()
+    _check(lib().eiger_skf_plan_join(_stats_array(build_stats), _stats_array(probe_stats), len(build_stats),
+                                     for_max_bits, dict_max_ndv, ctypes.byref(out)))
+    return out
+
+
+def _grow_dict_slots(plan: SkfPlanT) -> None:
+    for k in plan.key[: plan.n_keys]:
+        if k.code == SKF_DICT:
+            k.slots *= 8
+
+
+def _skf_call(fn, plan: SkfPlanT, n_rows: int, sort: int, device):
+    """Runs fn(plan, ws) -> rc, retrying with larger dictionary tables while the
+    library reports more distinct values than a table holds."""
+    while True:
+        need = ctypes.c_size_t()
+        _check(lib().eiger_skf_workspace_size(ctypes.byref(plan), n_rows, 0, sort, ctypes.byref(need)))
+        ws = _workspace(need.value, device)
+        rc = fn(plan, ws)
+        if rc == EIGER_ERR_TOO_LARGE and any(k.code == SKF_DICT and k.slots < (1 << 31)
+                                             for k in plan.key[: plan.n_keys]):
+            _grow_dict_slots(plan)
+            continue
+        _check(rc)
+        return
+
+
+def _fused_view(buf, plan: SkfPlanT, n: int):
+    import torch
+    return buf.view(torch.int32)[:n] if plan.fused_bytes == 4 else buf.view(torch.int64)[:n]
+
+
+def skf_fuse(keys_a, keys_b=None, plan: Optional[SkfPlanT] = None, stream=None):
+    """eiger_skf_fuse: one fused 4- or 8-byte key per row of one relation (or of
+    two, with one shared encoding). Without a plan, the keys' statistics are
+    computed and eiger_skf_plan (eiger_skf_plan_join for two relations) decides.
+    Returns (fused_a, fused_b or None, final plan); fused keys are int32/int64
+    tensors holding the unsigned fused bits."""
+    import torch
+    if plan is None:
+        if keys_b is None:
+            plan = skf_plan([stats(k, stream) for k in keys_a])
+        else:
+            plan = skf_plan_join([stats(k, stream) for k in keys_a], [stats(k, stream) for k in keys_b])
+    plan = SkfPlanT.from_buffer_copy(plan)
+    na = keys_a[0].numel()
+    nb = keys_b[0].numel() if keys_b is not None else 0
+    dev = keys_a[0].device
+    ca = (Column * len(keys_a))(*[column(t) for t in keys_a])
+    cb = (Column * len(keys_b))(*[column(t) for t in keys_b]) if keys_b is not None else None
+    oa = torch.empty(max(na, 1), dtype=torch.int64, device=dev)
+    ob = torch.empty(max(nb, 1), dtype=torch.int64, device=dev)
+    fin = SkfPlanT()
+
+    def run(pl, ws):
+        need = ctypes.c_size_t()
+        _check(lib().eiger_skf_workspace_size(ctypes.byref(pl), na, nb, 0, ctypes.byref(need)))
+        if ws.numel() < need.value:
+            ws = _workspace(need.value, dev)
+        return lib().eiger_skf_fuse(ca, cb, len(keys_a), ctypes.byref(pl), ctypes.c_void_p(oa.data_ptr()),
+                                    ctypes.c_void_p(ob.data_ptr()), ctypes.byref(fin),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream))
+
+    _skf_call(run, plan, na + nb, 0, dev)
+    return _fused_view(oa, fin, na), (_fused_view(ob, fin, nb) if keys_b is not None else None), fin
+
+
+def sort_multikey(keys, descending=None, plan: Optional[SkfPlanT] = None, with_sorted: bool = False, stream=None):
+    """eiger_sort_multikey: the stable sorting permutation of the rows by several
+    keys (each ascending or descending) through smart key fusion and one radix
+    sort. Returns (perm int32, sorted fused keys or None, final plan)."""
+    import torch
+    if plan is None:
+        plan = skf_plan([stats(k, stream) for k in keys], descending)
+    plan = SkfPlanT.from_buffer_copy(plan)
+    n = keys[0].numel()
+    dev = keys[0].device
+    ck = (Column * len(keys))(*[column(t) for t in keys])
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    srt = torch.empty(max(n, 1), dtype=torch.int64, device=dev) if with_sorted else None
+    fin = SkfPlanT()
+
+    def run(pl, ws):
+        return lib().eiger_sort_multikey(ck, len(keys), ctypes.byref(pl), ctypes.c_void_p(perm.data_ptr()),
+                                         ctypes.c_void_p(srt.data_ptr()) if srt is not None else None,
+                                         ctypes.byref(fin), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_ptr(stream))
+
+    _skf_call(run, plan, n, 1, dev)
+    return perm[:n], (_fused_view(srt, fin, n) if srt is not None else None), fin
+
+
+def dict_encode(col, slots: Optional[int] = None, stream=None):
+    """eiger_dict_encode: order-preserving dictionary codes of one column.
+    Returns (codes int32, dictionary in the column's dtype, ndv)."""
+    import torch
+    if slots is None:
+        est = stats(col, stream).ndv
+        slots = 1024
+        while slots < 2 * (1.05 * est + 16):
+            slots <<= 1
+    n = col.numel()
+    c = column(col)
+    codes = torch.empty(max(n, 1), dtype=torch.int32, device=col.device)
+    ndv = ctypes.c_int64()
+    while True:
+        need = ctypes.c_size_t()
+        _check(lib().eiger_dict_encode_workspace_size(c, slots, ctypes.byref(need)))
+        ws = _workspace(need.value, col.device)
+        cap = min(n, slots // 2) if n else 0
+        dic = torch.empty(max(cap, 1), dtype=col.dtype, device=col.device)
+        rc = lib().eiger_dict_encode(c, slots, ctypes.c_void_p(codes.data_ptr()), ctypes.c_void_p(dic.data_ptr()),
+                                     max(cap, 1), ctypes.byref(ndv), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream_ptr(stream))
+        if rc == EIGER_ERR_TOO_LARGE and slots < (1 << 31):
+            slots *= 8
+            continue
+        _check(rc)
+        return codes[:n], dic[: ndv.value], ndv.value
+
+
+def join_multikey(build_keys, probe_keys, build_payload=None, probe_payload=None, selector: int = SEL_RULE,
+                  stream=None):
+    """Equi-join on several key columns: smart key fusion of both relations with
+    one shared encoding, then the single-key join path (statistics, plan, join)
+    on the fused keys. Payloads default to the build / probe row ids' zeros.
+    Returns (JoinResult, fusion plan, join plan)."""
+    import torch
+    fa, fb, fin = skf_fuse(build_keys, probe_keys, stream=stream)
+    bp = build_payload if build_payload is not None else torch.zeros_like(fa)
+    pp = probe_payload if probe_payload is not None else torch.zeros_like(fb)
+    jp = join_plan(stats(fa, stream), stats(fb, stream), selector)
+    return join(fa, bp, fb, pp, jp, stream=stream), fin, jp
 
 
 MAT_GFUR, MAT_GFTR, MAT_AUTO = 0, 1, 2

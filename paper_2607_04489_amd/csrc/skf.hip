@@ -1,0 +1,608 @@
+// skf.hip -- smart key fusion (Section 4.3) and the order-preserving dictionary
+// encoding it uses (Algorithm 1).
+//
+// Dictionary encoding, per key column (one relation, or two read as one column):
+//   1. insert: every row inserts its key into an open-addressing table (CAS on an
+//      empty slot; the winner is the value's leader) and records its slot id;
+//   2. retrieve: the occupied slots are compacted into (value - min, slot) pairs,
+//      and their number is the exact distinct count;
+//   3. the pairs are radix-sorted by value (width of max - min);
+//   4. scatter: the slot of the i-th smallest value receives code i;
+//   5. gather: each row reads the code of its slot -- done inside the fusion
+//      kernel, so codes are never stored on their own.
+// The slot id plays the role of the leader's row id as group id: it indexes an
+// array of table size instead of one of column size, which stays in L2.
+//
+// Fusion: one kernel reads every key column (frame-of-reference keys) or slot
+// ids (dictionary keys) of a row, forms each code, complements it within its
+// width for a descending key, and ORs it into place: 4- or 8-byte output.
+#include <cmath>
+
+#include "common.hpp"
+#include "sort.hpp"
+
+namespace eiger {
+
+namespace {
+
+// INT64_MIN marks empty slots; rows holding that key use the extra slot `slots`.
+constexpr unsigned long long kDeEmpty = 0x8000000000000000ull;
+constexpr int kDeNT = 256;
+// Longest probe sequence an insert walks before it reports overflow: far beyond
+// what a table at most half full needs, and it bounds the work when the
+// distinct estimate was much too low (the caller then retries with more slots).
+constexpr uint64_t kDeMaxProbe = 2048;
+
+struct DeTable {
+  unsigned long long *key;  // slots entries
+  uint64_t mask;            // slots - 1
+  uint32_t *ctr;            // [0] distinct count, [1] INT64_MIN present, [2] overflow
+};
+
+// One logical column over the rows of one or two relations.
+template <typename K>
+struct Rows {
+  const K *a;
+  const K *b;
+  uint64_t na, n;
+  __device__ __forceinline__ const K *at(uint64_t i) const { return i < na ? a + i : b + (i - na); }
+};
+
+// Rows a fusion thread handles together: all their loads are issued before any
+// result is used, so each thread keeps several memory accesses in flight.
+constexpr int kDeBatch = 8;
+
+// One row per thread and step: a batched form (all rows' first table reads in
+// flight before any is resolved) measured slower on a hot, L2-resident table.
+template <typename K>
+__global__ void __launch_bounds__(kDeNT) k_de_insert(Rows<K> rows, DeTable t, uint32_t *__restrict__ loc) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDeNT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x; i < rows.n; i += stride) {
+    const unsigned long long k = static_cast<unsigned long long>(static_cast<int64_t>(*rows.at(i)));
+    uint64_t slot;
+    if (k == kDeEmpty) {
+      slot = t.mask + 1;
+      t.ctr[1] = 1u;
+    } else {
+      uint64_t h = fmix64(k) & t.mask;
+      slot = t.mask + 2;  // no slot: only reached with the overflow flag set
+      const uint64_t limit = t.mask < kDeMaxProbe ? t.mask + 1 : kDeMaxProbe;
+      for (uint64_t probe = 0; probe < limit; ++probe) {
+        unsigned long long cur = t.key[h];
+        if (cur == kDeEmpty) cur = atomicCAS(&t.key[h], kDeEmpty, k);
+        if (cur == kDeEmpty || cur == k) {
+          slot = h;
+          break;
+        }
+        h = (h + 1) & t.mask;
+      }
+      if (slot == t.mask + 2) t.ctr[2] = 1u;
+    }
+    loc[i] = static_cast<uint32_t>(slot);
+  }
+}
+
+// Compacts occupied slots into (key - base, slot) pairs; one atomic per wave.
+__global__ void __launch_bounds__(kDeNT) k_de_retrieve(DeTable t, uint64_t base, unsigned long long *__restrict__ ukey,
+                                                       uint32_t *__restrict__ uslot) {
+  const uint64_t slots = t.mask + 1;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDeNT;
+  const uint64_t first = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x;
+  // every lane of a wave runs the same number of iterations (ballots below)
+  const uint64_t wave0 = first - __lane_id();
+  for (uint64_t i0 = wave0; i0 < slots; i0 += stride) {
+    const uint64_t i = i0 + __lane_id();
+    const unsigned long long k = i < slots ? t.key[i] : kDeEmpty;
+    const bool occ = k != kDeEmpty;
+    const uint64_t m = __ballot(occ);
+    uint32_t at = 0;
+    if (__lane_id() == 0 && m) at = atomicAdd(&t.ctr[0], static_cast<uint32_t>(__popcll(m)));
+    at = __shfl(at, 0, 64) + lane_prefix(m);
+    if (occ) {
+      ukey[at] = k - base;
+      uslot[at] = static_cast<uint32_t>(i);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && t.ctr[1]) {
+    const uint32_t at = atomicAdd(&t.ctr[0], 1u);
+    ukey[at] = kDeEmpty - base;
+    uslot[at] = static_cast<uint32_t>(slots);
+  }
+}
+
+// Step 4: the slot of the i-th smallest distinct value gets code i.
+__global__ void __launch_bounds__(kDeNT) k_de_scatter(const uint32_t *__restrict__ sorted_slot, uint64_t ndv,
+                                                      uint32_t *__restrict__ code_of_slot) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x;
+  if (i < ndv) code_of_slot[sorted_slot[i]] = static_cast<uint32_t>(i);
+}
+
+// Step 5 for the stand-alone encoding, and the dictionary itself.
+__global__ void __launch_bounds__(kDeNT) k_de_gather(const uint32_t *__restrict__ loc, uint64_t n,
+                                                     const uint32_t *__restrict__ code_of_slot,
+                                                     uint32_t *__restrict__ codes) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDeNT;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x; i < n; i += stride)
+    codes[i] = code_of_slot[loc[i]];
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kDeNT) k_de_dict(const unsigned long long *__restrict__ sorted_key, uint64_t ndv,
+                                                   uint64_t base, K *__restrict__ dict) {
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x;
+  if (i < ndv) dict[i] = static_cast<K>(static_cast<int64_t>(sorted_key[i] + base));
+}
+
+struct FuseKey {
+  const void *a;
+  const void *b;
+  const uint32_t *loc;           // DICT: slot of each row
+  const uint32_t *code_of_slot;  // DICT: code of each slot
+  uint64_t base;                 // FOR: minimum (two's-complement bits)
+  uint64_t flip;                 // all-ones over the width for a descending key, else 0
+  int32_t wide;                  // 8-byte key column
+  int32_t dict;
+  int32_t bits;
+  int32_t shift;
+};
+
+struct FuseArgs {
+  FuseKey k[EIGER_SKF_MAX_KEYS];
+  int32_t nk;
+  uint64_t na, n;
+  void *out_a;
+  void *out_b;
+};
+
+template <typename F>
+__global__ void __launch_bounds__(kDeNT) k_skf_fuse(FuseArgs A) {
+  constexpr uint64_t span = uint64_t(kDeNT) * kDeBatch;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * span;
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * span + threadIdx.x; base < A.n;
+       base += stride) {
+    F f[kDeBatch];
+#pragma unroll
+    for (int b = 0; b < kDeBatch; ++b) f[b] = 0;
+    for (int c = 0; c < A.nk; ++c) {
+      const FuseKey &k = A.k[c];
+      if (k.bits == 0) continue;
+      uint64_t code[kDeBatch];
+      if (k.dict) {
+        uint32_t sl[kDeBatch];
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) {
+          const uint64_t i = base + uint64_t(b) * kDeNT;
+          sl[b] = i < A.n ? k.loc[i] : 0u;
+        }
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) {
+          const uint64_t i = base + uint64_t(b) * kDeNT;
+          code[b] = i < A.n ? k.code_of_slot[sl[b]] : 0u;
+        }
+      } else if (k.wide) {
+        int64_t v[kDeBatch];
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) {
+          const uint64_t i = base + uint64_t(b) * kDeNT;
+          if (i < A.n) v[b] = i < A.na ? static_cast<const int64_t *>(k.a)[i] : static_cast<const int64_t *>(k.b)[i - A.na];
+        }
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) code[b] = static_cast<uint64_t>(v[b]) - k.base;
+      } else {
+        int32_t v[kDeBatch];
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) {
+          const uint64_t i = base + uint64_t(b) * kDeNT;
+          if (i < A.n) v[b] = i < A.na ? static_cast<const int32_t *>(k.a)[i] : static_cast<const int32_t *>(k.b)[i - A.na];
+        }
+        // exact: every key is at least the minimum
+#pragma unroll
+        for (int b = 0; b < kDeBatch; ++b) code[b] = static_cast<uint64_t>(static_cast<int64_t>(v[b])) - k.base;
+      }
+#pragma unroll
+      for (int b = 0; b < kDeBatch; ++b) f[b] |= static_cast<F>((code[b] ^ k.flip) << k.shift);
+    }
+#pragma unroll
+    for (int b = 0; b < kDeBatch; ++b) {
+      const uint64_t i = base + uint64_t(b) * kDeNT;
+      if (i < A.na)
+        static_cast<F *>(A.out_a)[i] = f[b];
+      else if (i < A.n)
+        static_cast<F *>(A.out_b)[i - A.na] = f[b];
+    }
+  }
+}
+
+unsigned grid_for(uint64_t n, int nt = kDeNT) {
+  const uint64_t blocks = (n + nt - 1) / nt;
+  return static_cast<unsigned>(std::max<uint64_t>(1, std::min<uint64_t>(blocks, 8192)));
+}
+
+int bit_width_u64(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+uint64_t de_slots(double est) {
+  uint64_t s = 1024;
+  while (static_cast<double>(s) < 2.0 * (1.05 * est + 16.0)) s <<= 1;
+  return s;
+}
+
+void plan_shifts(eiger_skf_plan_t *p) {
+  int total = 0;
+  for (int c = 0; c < p->n_keys; ++c) total += p->key[c].bits;
+  p->total_bits = total;
+  p->fused_bytes = total <= 32 ? 4 : (total <= 64 ? 8 : 0);
+  int pos = total;
+  for (int c = 0; c < p->n_keys; ++c) {
+    pos -= p->key[c].bits;
+    p->key[c].shift = pos;
+  }
+}
+
+void plan_key(const eiger_stats_t &st, int descending, int for_max_bits, int64_t dict_max_ndv, eiger_skf_key_t *k) {
+  *k = eiger_skf_key_t{};
+  k->dtype = st.dtype;
+  k->descending = descending ? 1 : 0;
+  if (st.n == 0) {
+    k->code = EIGER_SKF_FOR;
+    return;
+  }
+  const uint64_t range = static_cast<uint64_t>(st.max) - static_cast<uint64_t>(st.min);
+  const int w = bit_width_u64(range);
+  k->base = st.min;
+  k->range_bits = w;
+  if (w <= for_max_bits) {
+    k->code = EIGER_SKF_FOR;
+    k->bits = w;
+  } else if (st.ndv <= static_cast<double>(dict_max_ndv)) {
+    const double est = std::max(1.0, st.ndv);
+    k->code = EIGER_SKF_DICT;
+    k->ndv = static_cast<int64_t>(std::llround(est));
+    k->slots = static_cast<int64_t>(de_slots(est));
+    k->bits = bit_width_u64(static_cast<uint64_t>(std::max<int64_t>(k->ndv, 1) - 1));
+  } else {
+    k->code = EIGER_SKF_FOR;
+    k->bits = w;
+  }
+}
+
+int check_plan(const eiger_skf_plan_t *p, const char *who) {
+  if (!p || p->n_keys < 1 || p->n_keys > EIGER_SKF_MAX_KEYS)
+    return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": plan with 1..8 keys expected");
+  for (int c = 0; c < p->n_keys; ++c) {
+    const eiger_skf_key_t &k = p->key[c];
+    if (k.dtype != EIGER_INT32 && k.dtype != EIGER_INT64)
+      return fail(EIGER_ERR_DTYPE, std::string(who) + ": key dtype must be int32 or int64");
+    if (k.code == EIGER_SKF_DICT) {
+      if (k.slots < 2 || (k.slots & (k.slots - 1)) || k.slots > (int64_t(1) << 31))
+        return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": dictionary slots must be a power of two <= 2^31");
+      if (k.range_bits < 0 || k.range_bits > 64) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": range_bits");
+    } else if (k.code != EIGER_SKF_FOR || k.bits < 0 || k.bits > 64) {
+      return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": bad key code or width");
+    }
+  }
+  return EIGER_OK;
+}
+
+// Per dictionary key: the table, the slot of every row, the sorted distinct
+// values with their slots, and the code of every slot.
+struct DictBufs {
+  DeTable t;
+  uint32_t *loc;
+  unsigned long long *ukey, *skey;
+  uint32_t *uslot, *sslot, *code_of_slot;
+};
+
+struct SkfLayout {
+  DictBufs d[EIGER_SKF_MAX_KEYS];
+  uint32_t *ctr;  // 4 words per key
+  void *fused;    // sort: fused keys before sorting
+  void *sorted;   // sort: sorted keys when the caller passes none
+};
+
+// Sizes the sort workspace for the largest distinct-value sort and the row sort.
+size_t sort_ws_bytes(int key_bytes, uint64_t n, int bits) {
+  Workspace w(nullptr, 0);
+  radix_sort_pairs(key_bytes, nullptr, nullptr, n, bits, nullptr, nullptr, w, nullptr);
+  return w.used + 256;
+}
+
+size_t skf_layout(Workspace &ws, const eiger_skf_plan_t &p, uint64_t n, bool sort, SkfLayout *L) {
+  *L = SkfLayout{};
+  L->ctr = ws.take<uint32_t>(4 * EIGER_SKF_MAX_KEYS);
+  uint64_t max_slots = 0;
+  for (int c = 0; c < p.n_keys; ++c) {
+    if (p.key[c].code != EIGER_SKF_DICT) continue;
+    const uint64_t slots = static_cast<uint64_t>(p.key[c].slots);
+    max_slots = std::max(max_slots, slots);
+    DictBufs &d = L->d[c];
+    d.t.key = ws.take<unsigned long long>(slots);
+    d.t.mask = slots - 1;
+    d.t.ctr = L->ctr ? L->ctr + 4 * c : nullptr;
+    d.loc = ws.take<uint32_t>(n);
+    d.ukey = ws.take<unsigned long long>(slots + 1);
+    d.skey = ws.take<unsigned long long>(slots + 1);
+    d.uslot = ws.take<uint32_t>(slots + 1);
+    d.sslot = ws.take<uint32_t>(slots + 1);
+    d.code_of_slot = ws.take<uint32_t>(slots + 1);
+  }
+  if (sort) {
+    L->fused = ws.take<uint64_t>(n);
+    L->sorted = ws.take<uint64_t>(n);
+  }
+  // one shared region for every radix sort of this call (they run one after another)
+  const size_t need = std::max(max_slots ? sort_ws_bytes(8, max_slots + 1, 64) : 0,
+                               sort ? sort_ws_bytes(8, n, 64) : 0);
+  return need;
+}
+
+template <typename K>
+int de_launch_insert(const DictBufs &d, const void *a, const void *b, uint64_t na, uint64_t n, hipStream_t s) {
+  Rows<K> r{static_cast<const K *>(a), static_cast<const K *>(b), na, n};
+  EIGER_LAUNCH("dict_insert", k_de_insert<K>, dim3(grid_for(n)), dim3(kDeNT), 0, s, r, d.t, d.loc);
+  return EIGER_OK;
+}
+
+// Steps 1-2 for every dictionary key, one read-back of the counts, then steps 3-4.
+// Fills the exact counts and widths into *out.
+int dict_steps(const eiger_skf_plan_t &p, const eiger_column *ka, const eiger_column *kb, uint64_t na, uint64_t n,
+               SkfLayout &L, void *sort_ws, size_t sort_ws_size, eiger_skf_plan_t *out, hipStream_t s) {
+  bool any = false;
+  for (int c = 0; c < p.n_keys; ++c) {
+    if (p.key[c].code != EIGER_SKF_DICT) continue;
+    any = true;
+    DictBufs &d = L.d[c];
+    int rc = fill_u64(reinterpret_cast<uint64_t *>(d.t.key), d.t.mask + 1, kDeEmpty, s);
+    if (rc) return rc;
+    if ((rc = fill_u32(d.t.ctr, 4, 0u, s))) return rc;
+    const void *a = ka[c].data, *b = kb ? kb[c].data : nullptr;
+    rc = p.key[c].dtype == EIGER_INT64 ? de_launch_insert<int64_t>(d, a, b, na, n, s)
+                                       : de_launch_insert<int32_t>(d, a, b, na, n, s);
+    if (rc) return rc;
+    EIGER_LAUNCH("dict_retrieve", k_de_retrieve, dim3(grid_for(d.t.mask + 1)), dim3(kDeNT), 0, s, d.t,
+                 static_cast<uint64_t>(p.key[c].base), d.ukey, d.uslot);
+  }
+  *out = p;
+  if (!any) return EIGER_OK;
+  uint32_t host[4 * EIGER_SKF_MAX_KEYS];
+  EIGER_HIP(hipMemcpyAsync(host, L.ctr, sizeof(host), hipMemcpyDeviceToHost, s));
+  EIGER_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < p.n_keys; ++c) {
+    if (p.key[c].code != EIGER_SKF_DICT) continue;
+    const uint64_t ndv = host[4 * c];
+    if (host[4 * c + 2] || ndv > static_cast<uint64_t>(p.key[c].slots) / 2)
+      return fail(EIGER_ERR_TOO_LARGE, "smart key fusion: more distinct values than half the dictionary slots");
+    out->key[c].ndv = static_cast<int64_t>(ndv);
+    out->key[c].bits = bit_width_u64(ndv ? ndv - 1 : 0);
+  }
+  plan_shifts(out);
+  for (int c = 0; c < p.n_keys; ++c) {
+    if (p.key[c].code != EIGER_SKF_DICT) continue;
+    DictBufs &d = L.d[c];
+    const uint64_t ndv = static_cast<uint64_t>(out->key[c].ndv);
+    Workspace sw(sort_ws, sort_ws_size);
+    int rc = radix_sort_pairs(8, d.ukey, d.uslot, ndv, p.key[c].range_bits, d.skey, d.sslot, sw, s);
+    if (rc) return rc;
+    if (ndv)
+      EIGER_LAUNCH("dict_scatter", k_de_scatter, dim3(grid_for(ndv)), dim3(kDeNT), 0, s, d.sslot, ndv,
+                   d.code_of_slot);
+  }
+  return EIGER_OK;
+}
+
+int launch_fuse(const eiger_skf_plan_t &p, const eiger_column *ka, const eiger_column *kb, uint64_t na, uint64_t n,
+                const SkfLayout &L, void *out_a, void *out_b, hipStream_t s) {
+  if (n == 0) return EIGER_OK;
+  FuseArgs A{};
+  A.nk = p.n_keys;
+  A.na = na;
+  A.n = n;
+  A.out_a = out_a;
+  A.out_b = out_b;
+  for (int c = 0; c < p.n_keys; ++c) {
+    const eiger_skf_key_t &k = p.key[c];
+    FuseKey &f = A.k[c];
+    f.a = ka[c].data;
+    f.b = kb ? kb[c].data : nullptr;
+    f.wide = k.dtype == EIGER_INT64;
+    f.dict = k.code == EIGER_SKF_DICT;
+    f.loc = L.d[c].loc;
+    f.code_of_slot = L.d[c].code_of_slot;
+    f.base = static_cast<uint64_t>(k.base);
+    f.bits = k.bits;
+    f.shift = k.shift;
+    f.flip = k.descending && k.bits ? (k.bits == 64 ? ~0ull : ((1ull << k.bits) - 1)) : 0ull;
+  }
+  const unsigned grid = grid_for((n + kDeBatch - 1) / kDeBatch);
+  if (p.fused_bytes == 4) {
+    EIGER_LAUNCH("skf_fuse", k_skf_fuse<uint32_t>, dim3(grid), dim3(kDeNT), 0, s, A);
+  } else {
+    EIGER_LAUNCH("skf_fuse", k_skf_fuse<uint64_t>, dim3(grid), dim3(kDeNT), 0, s, A);
+  }
+  return EIGER_OK;
+}
+
+int check_keys(const eiger_column *keys, int32_t n_keys, const eiger_skf_plan_t &p, int64_t *n, const char *who) {
+  if (!keys) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": NULL key array");
+  if (n_keys != p.n_keys) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": n_keys differs from the plan");
+  *n = keys[0].n;
+  for (int c = 0; c < n_keys; ++c) {
+    if (keys[c].n != *n) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": key columns of unequal length");
+    if (keys[c].dtype != p.key[c].dtype) return fail(EIGER_ERR_DTYPE, std::string(who) + ": key dtype differs from the plan");
+    if (keys[c].n > 0 && !keys[c].data) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": NULL key column");
+  }
+  if (*n < 0 || *n > EIGER_MAX_ROWS) return fail(EIGER_ERR_TOO_LARGE, std::string(who) + ": rows outside [0, EIGER_MAX_ROWS]");
+  return EIGER_OK;
+}
+
+size_t skf_total_bytes(const eiger_skf_plan_t &p, uint64_t n, bool sort) {
+  Workspace ws(nullptr, 0);
+  SkfLayout L;
+  const size_t sort_need = skf_layout(ws, p, n, sort, &L);
+  ws.take<char>(sort_need);
+  return ws.used + 256;
+}
+
+// eiger_skf_fuse and eiger_sort_multikey share this body.
+int skf_run(const eiger_column *ka, const eiger_column *kb, int32_t n_keys, const eiger_skf_plan_t *plan, void *out_a,
+            void *out_b, bool sort, uint32_t *perm, void *sorted, eiger_skf_plan_t *out_plan, void *wsp,
+            size_t ws_bytes, hipStream_t s, const char *who) {
+  if (int rc = check_plan(plan, who)) return rc;
+  if (!out_plan) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": out_plan is NULL");
+  int64_t na = 0, nb = 0;
+  if (int rc = check_keys(ka, n_keys, *plan, &na, who)) return rc;
+  if (kb)
+    if (int rc = check_keys(kb, n_keys, *plan, &nb, who)) return rc;
+  const uint64_t n = static_cast<uint64_t>(na + nb);
+  if (n > static_cast<uint64_t>(EIGER_MAX_ROWS)) return fail(EIGER_ERR_TOO_LARGE, std::string(who) + ": too many rows");
+  if (n > 0 && !sort && (!out_a || (nb > 0 && !out_b)))
+    return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": NULL output");
+  if (n > 0 && sort && !perm) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": out_perm is NULL");
+  if (ws_bytes < skf_total_bytes(*plan, n, sort))
+    return fail(EIGER_ERR_WORKSPACE, std::string(who) + ": workspace too small");
+  if (n > 0 && !wsp) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": NULL workspace");
+  Workspace ws(wsp, ws_bytes);
+  SkfLayout L;
+  const size_t sort_need = skf_layout(ws, *plan, n, sort, &L);
+  void *sort_ws = ws.take<char>(sort_need);
+  int rc = dict_steps(*plan, ka, kb, static_cast<uint64_t>(na), n, L, sort_ws, sort_need, out_plan, s);
+  if (rc) return rc;
+  if (out_plan->fused_bytes == 0)
+    return fail(EIGER_ERR_UNSUPPORTED, std::string(who) + ": the key codes need more than 64 bits");
+  if (!sort) return launch_fuse(*out_plan, ka, kb, static_cast<uint64_t>(na), n, L, out_a, out_b, s);
+  if ((rc = launch_fuse(*out_plan, ka, nullptr, n, n, L, L.fused, nullptr, s))) return rc;
+  Workspace sw(sort_ws, sort_need);
+  return radix_sort_pairs(out_plan->fused_bytes, L.fused, nullptr, n, out_plan->total_bits,
+                          sorted ? sorted : L.sorted, perm, sw, s);
+}
+
+}  // namespace
+
+}  // namespace eiger
+
+using namespace eiger;
+
+extern "C" int eiger_skf_plan(const eiger_stats_t *stats, const int32_t *descending, int32_t n_keys,
+                              int32_t for_max_bits, int64_t dict_max_ndv, eiger_skf_plan_t *out) {
+  if (!stats || !out) return fail(EIGER_ERR_INVALID_ARG, "eiger_skf_plan: NULL argument");
+  if (n_keys < 1 || n_keys > EIGER_SKF_MAX_KEYS) return fail(EIGER_ERR_INVALID_ARG, "eiger_skf_plan: 1..8 keys");
+  eiger_skf_plan_t p{};
+  p.n_keys = n_keys;
+  for (int c = 0; c < n_keys; ++c) {
+    if (stats[c].dtype != EIGER_INT32 && stats[c].dtype != EIGER_INT64)
+      return fail(EIGER_ERR_DTYPE, "eiger_skf_plan: key dtype must be int32 or int64");
+    plan_key(stats[c], descending ? descending[c] : 0, for_max_bits, dict_max_ndv, &p.key[c]);
+  }
+  plan_shifts(&p);
+  *out = p;
+  return EIGER_OK;
+}
+
+extern "C" int eiger_skf_plan_join(const eiger_stats_t *build_stats, const eiger_stats_t *probe_stats, int32_t n_keys,
+                                   int32_t for_max_bits, int64_t dict_max_ndv, eiger_skf_plan_t *out) {
+  if (!build_stats || !probe_stats || !out) return fail(EIGER_ERR_INVALID_ARG, "eiger_skf_plan_join: NULL argument");
+  if (n_keys < 1 || n_keys > EIGER_SKF_MAX_KEYS) return fail(EIGER_ERR_INVALID_ARG, "eiger_skf_plan_join: 1..8 keys");
+  eiger_skf_plan_t p{};
+  p.n_keys = n_keys;
+  for (int c = 0; c < n_keys; ++c) {
+    const eiger_stats_t &b = build_stats[c], &q = probe_stats[c];
+    if (b.dtype != q.dtype || (b.dtype != EIGER_INT32 && b.dtype != EIGER_INT64))
+      return fail(EIGER_ERR_DTYPE, "eiger_skf_plan_join: both sides' key dtypes must match (int32 or int64)");
+    eiger_stats_t u = b;
+    u.n = b.n + q.n;
+    if (b.n == 0) {
+      u.min = q.min;
+      u.max = q.max;
+    } else if (q.n > 0) {
+      u.min = std::min(b.min, q.min);
+      u.max = std::max(b.max, q.max);
+    }
+    u.ndv = b.ndv + q.ndv;  // at least the distinct count of the union
+    plan_key(u, 0, for_max_bits, dict_max_ndv, &p.key[c]);
+  }
+  plan_shifts(&p);
+  *out = p;
+  return EIGER_OK;
+}
+
+extern "C" int eiger_skf_workspace_size(const eiger_skf_plan_t *plan, int64_t n_a, int64_t n_b, int32_t sort,
+                                        size_t *bytes) {
+  if (!bytes) return fail(EIGER_ERR_INVALID_ARG, "eiger_skf_workspace_size: bytes is NULL");
+  if (int rc = check_plan(plan, "eiger_skf_workspace_size")) return rc;
+  if (n_a < 0 || n_b < 0 || n_a + n_b > EIGER_MAX_ROWS)
+    return fail(EIGER_ERR_TOO_LARGE, "eiger_skf_workspace_size: rows outside [0, EIGER_MAX_ROWS]");
+  *bytes = skf_total_bytes(*plan, static_cast<uint64_t>(n_a + n_b), sort != 0);
+  return EIGER_OK;
+}
+
+extern "C" int eiger_skf_fuse(const eiger_column *keys_a, const eiger_column *keys_b, int32_t n_keys,
+                              const eiger_skf_plan_t *plan, void *out_a, void *out_b, eiger_skf_plan_t *out_plan,
+                              void *ws, size_t ws_bytes, void *stream) {
+  return skf_run(keys_a, keys_b, n_keys, plan, out_a, out_b, false, nullptr, nullptr, out_plan, ws, ws_bytes,
+                 static_cast<hipStream_t>(stream), "eiger_skf_fuse");
+}
+
+extern "C" int eiger_sort_multikey(const eiger_column *keys, int32_t n_keys, const eiger_skf_plan_t *plan,
+                                   uint32_t *out_perm, void *out_sorted, eiger_skf_plan_t *out_plan, void *ws,
+                                   size_t ws_bytes, void *stream) {
+  return skf_run(keys, nullptr, n_keys, plan, nullptr, nullptr, true, out_perm, out_sorted, out_plan, ws, ws_bytes,
+                 static_cast<hipStream_t>(stream), "eiger_sort_multikey");
+}
+
+extern "C" int eiger_dict_encode_workspace_size(eiger_column col, int64_t slots, size_t *bytes) {
+  if (!bytes) return fail(EIGER_ERR_INVALID_ARG, "eiger_dict_encode_workspace_size: bytes is NULL");
+  if (col.n < 0 || col.n > EIGER_MAX_ROWS) return fail(EIGER_ERR_TOO_LARGE, "eiger_dict_encode: rows outside range");
+  eiger_skf_plan_t p{};
+  p.n_keys = 1;
+  p.key[0].code = EIGER_SKF_DICT;
+  p.key[0].dtype = col.dtype;
+  p.key[0].slots = slots;
+  p.key[0].range_bits = 64;
+  if (int rc = check_plan(&p, "eiger_dict_encode")) return rc;
+  *bytes = skf_total_bytes(p, static_cast<uint64_t>(col.n), false);
+  return EIGER_OK;
+}
+
+extern "C" int eiger_dict_encode(eiger_column col, int64_t slots, uint32_t *out_codes, void *out_dict,
+                                 int64_t dict_capacity, int64_t *out_ndv, void *wsp, size_t ws_bytes, void *stream) {
+  size_t need = 0;
+  if (int rc = eiger_dict_encode_workspace_size(col, slots, &need)) return rc;
+  if (!out_ndv) return fail(EIGER_ERR_INVALID_ARG, "eiger_dict_encode: out_ndv is NULL");
+  if (col.n > 0 && (!col.data || !out_codes || !wsp)) return fail(EIGER_ERR_INVALID_ARG, "eiger_dict_encode: NULL buffer");
+  if (ws_bytes < need) return fail(EIGER_ERR_WORKSPACE, "eiger_dict_encode: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  eiger_skf_plan_t p{};
+  p.n_keys = 1;
+  p.key[0].code = EIGER_SKF_DICT;
+  p.key[0].dtype = col.dtype;
+  p.key[0].slots = slots;
+  p.key[0].range_bits = 64;  // values are sorted as key - INT64_MIN over the full width
+  p.key[0].base = INT64_MIN;
+  *out_ndv = 0;
+  if (col.n == 0) return EIGER_OK;
+  Workspace ws(wsp, ws_bytes);
+  SkfLayout L;
+  const size_t sort_need = skf_layout(ws, p, static_cast<uint64_t>(col.n), false, &L);
+  void *sort_ws = ws.take<char>(sort_need);
+  eiger_skf_plan_t fin;
+  int rc = dict_steps(p, &col, nullptr, static_cast<uint64_t>(col.n), static_cast<uint64_t>(col.n), L, sort_ws,
+                      sort_need, &fin, s);
+  if (rc) return rc;
+  const uint64_t ndv = static_cast<uint64_t>(fin.key[0].ndv);
+  *out_ndv = fin.key[0].ndv;
+  if (out_dict && fin.key[0].ndv > dict_capacity)
+    return fail(EIGER_ERR_CAPACITY, "eiger_dict_encode: more distinct values than dict_capacity");
+  const DictBufs &d = L.d[0];
+  EIGER_LAUNCH("dict_gather", k_de_gather, dim3(grid_for(static_cast<uint64_t>(col.n))), dim3(kDeNT), 0, s, d.loc,
+               static_cast<uint64_t>(col.n), d.code_of_slot, out_codes);
+  if (out_dict) {
+    if (col.dtype == EIGER_INT64) {
+      EIGER_LAUNCH("dict_values", k_de_dict<int64_t>, dim3(grid_for(ndv)), dim3(kDeNT), 0, s, d.skey, ndv,
+                   static_cast<uint64_t>(INT64_MIN), static_cast<int64_t *>(out_dict));
+    } else {
+      EIGER_LAUNCH("dict_values", k_de_dict<int32_t>, dim3(grid_for(ndv)), dim3(kDeNT), 0, s, d.skey, ndv,
+                   static_cast<uint64_t>(INT64_MIN), static_cast<int32_t *>(out_dict));
+    }
+  }
+  EIGER_HIP(hipStreamSynchronize(s));
+  return EIGER_OK;
+}

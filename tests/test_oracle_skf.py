@@ -144,3 +144,12 @@ def test_join_multikey_against_double_loop(seed):
 
 def test_join_multikey_empty_side():
     assert skf.join_multikey([np.zeros(0, np.int64)], [np.arange(3)]).size == 0
+
+
+def test_sort_pairs_is_stable_and_masks():
+    keys = np.array([5, 3, 5 + 16, 3, 0, 15], dtype=np.uint32)
+    k, perm = skf.sort_pairs(keys, 4)        # 5 + 16 has low 4 bits 5
+    assert k.tolist() == [0, 3, 3, 5, 5, 15]
+    assert perm.tolist() == [4, 1, 3, 0, 2, 5]
+    k, perm = skf.sort_pairs(np.array([-1, 0, 1], dtype=np.int64), 64)   # unsigned order
+    assert perm.tolist() == [1, 2, 0]
