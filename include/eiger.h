@@ -90,8 +90,10 @@ typedef enum {
     EIGER_DIRECT = 0,      /* table indexed by key - min; needs a dense build key range */
     EIGER_GLOBAL_HASH = 1, /* one open-addressing table in HBM (non-partitioned hash join) */
     EIGER_RADIX = 2,       /* hash-radix partitioning, then LDS-resident tables per partition */
-    EIGER_RADIX_CACHE = 3  /* one partitioning pass of the probe side; one partition-major table in
+    EIGER_RADIX_CACHE = 3, /* one partitioning pass of the probe side; one partition-major table in
                               HBM whose per-partition regions are read from one XCD's L2 at a time */
+    EIGER_SORT_MERGE = 4   /* both sides radix-sorted on key - build_min, then merged (Section 3.2,
+                              Table 1); needs the plan's build_min/build_max to cover the build keys */
 } eiger_variant;
 
 typedef enum {

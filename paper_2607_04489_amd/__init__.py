@@ -31,8 +31,9 @@ EIGER_ERR_UNSUPPORTED = -7
 EIGER_ERR_MODEL = -8
 
 INT32, INT64 = 0, 1
-DIRECT, GLOBAL_HASH, RADIX, RADIX_CACHE = 0, 1, 2, 3
-VARIANT_NAMES = {DIRECT: "direct", GLOBAL_HASH: "global_hash", RADIX: "radix", RADIX_CACHE: "radix_cache"}
+DIRECT, GLOBAL_HASH, RADIX, RADIX_CACHE, SORT_MERGE = 0, 1, 2, 3, 4
+VARIANT_NAMES = {DIRECT: "direct", GLOBAL_HASH: "global_hash", RADIX: "radix", RADIX_CACHE: "radix_cache",
+                 SORT_MERGE: "sort_merge"}
 SEL_RULE, SEL_LEARNED, SEL_FIXED_HASH, SEL_FORCED = 0, 1, 2, 3
 PLAN_RULE_FALLBACK = 1
 HLL_P = 14

@@ -138,7 +138,7 @@ int check_join_inputs(const eiger_column &bk, const eiger_column &bp, const eige
   if (bk.n != bp.n) return fail(EIGER_ERR_INVALID_ARG, "build_payload has a different row count than build_keys");
   if (pk.n != pp.n) return fail(EIGER_ERR_INVALID_ARG, "probe_payload has a different row count than probe_keys");
   if (!plan) return fail(EIGER_ERR_INVALID_ARG, "plan is NULL");
-  if (plan->variant < EIGER_DIRECT || plan->variant > EIGER_RADIX_CACHE)
+  if (plan->variant < EIGER_DIRECT || plan->variant > EIGER_SORT_MERGE)
     return fail(EIGER_ERR_INVALID_ARG, "plan.variant is not an eiger_variant");
   if (plan->key_dtype != bk.dtype) return fail(EIGER_ERR_DTYPE, "plan.key_dtype differs from the key columns");
   if (plan->variant == EIGER_DIRECT && bk.n > 0) {
@@ -148,7 +148,10 @@ int check_join_inputs(const eiger_column &bk, const eiger_column &bp, const eige
     if (range == 0 || range > kDirectMaxRange)
       return fail(EIGER_ERR_UNSUPPORTED, "DIRECT plan: key range above 2^30 values");
   }
-  if (plan->variant != EIGER_DIRECT && !(plan->load_factor > 0.f && plan->load_factor <= 0.9f))
+  if (plan->variant == EIGER_SORT_MERGE && bk.n > 0 && plan->build_max < plan->build_min)
+    return fail(EIGER_ERR_INVALID_ARG, "SORT_MERGE plan: build_max < build_min");
+  if (plan->variant != EIGER_DIRECT && plan->variant != EIGER_SORT_MERGE &&
+      !(plan->load_factor > 0.f && plan->load_factor <= 0.9f))
     return fail(EIGER_ERR_INVALID_ARG, "plan.load_factor must be in (0, 0.9]");
   if (plan->variant == EIGER_RADIX) {
     if (plan->radix_bits < 1 || plan->radix_bits > 18)
@@ -187,6 +190,7 @@ int run_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
     case EIGER_DIRECT: return run_direct(a, ws, ctr);
     case EIGER_GLOBAL_HASH: return run_global_hash(a, ws, ctr);
     case EIGER_RADIX: return run_radix(a, ws, ctr);
+    case EIGER_SORT_MERGE: return run_sort_merge(a, ws, ctr);
     default: return run_radix_cache(a, ws, ctr);
   }
 }
@@ -330,7 +334,7 @@ extern "C" int eiger_join_plan(const eiger_stats_t *build, const eiger_stats_t *
       break;
     case EIGER_SEL_FORCED:
       if (!forced) return fail(EIGER_ERR_INVALID_ARG, "eiger_join_plan: EIGER_SEL_FORCED needs `forced`");
-      if (forced->variant < EIGER_DIRECT || forced->variant > EIGER_RADIX_CACHE)
+      if (forced->variant < EIGER_DIRECT || forced->variant > EIGER_SORT_MERGE)
         return fail(EIGER_ERR_INVALID_ARG, "eiger_join_plan: forced.variant is not an eiger_variant");
       p.variant = forced->variant;
       p.load_factor = forced->load_factor;

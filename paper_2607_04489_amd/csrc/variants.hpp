@@ -32,6 +32,7 @@ int run_direct(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_global_hash(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 int run_radix_cache(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
+int run_sort_merge(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 
 // Wide joins: payload columns as 32-bit word lanes (an 8-byte column is two
 // lanes, low word then high word, each with stride 2).

@@ -27,6 +27,7 @@ SPECS = [
     ("cache_b1", eg.RADIX_CACHE, 1, 1, 0.5),
     ("cache_b6", eg.RADIX_CACHE, 6, 1, 0.75),
     ("cache_b10", eg.RADIX_CACHE, 10, 1, 0.5),
+    ("sort_merge", eg.SORT_MERGE, 0, 0, 0.0),
 ]
 SPEC_IDS = [s[0] for s in SPECS]
 

@@ -19,6 +19,7 @@ PLANS = [
     ("radix_b6", eg.RADIX, 6, 1, 0.5, (eg.MAT_GFUR, eg.MAT_GFTR)),
     ("radix_b12p2", eg.RADIX, 12, 2, 0.25, (eg.MAT_GFUR, eg.MAT_GFTR)),
     ("cache_b6", eg.RADIX_CACHE, 6, 1, 0.5, (eg.MAT_GFUR,)),
+    ("sort_merge", eg.SORT_MERGE, 0, 0, 0.0, (eg.MAT_GFUR,)),
 ]
 
 
