@@ -438,6 +438,56 @@ def bench_skf_sort(n_log2=28, reps=3, seed=42, configs=((4, "int32"), (2, "int32
                         "over the type's range; all ascending"}
 
 
+def bench_join_sweep(reps=3, seed=42):
+    """The paper's narrow-join microbenchmarks (Section 5.2: |S| = 2^28 with |R|
+    varied, and |R| = 2^16 with |S| varied; unique build keys, every probe row
+    matching, a key and one payload column per side of the key's width), timed
+    per plan: the hash join (GLOBAL_HASH lf 0.5), the partitioned hash join
+    (RADIX, bits from the planner), the sort-merge join (SORT_MERGE) and the
+    rule's own choice. Each cell is the minimum of `reps` runs after one
+    warm-up; one run = one eiger_join call (statistics excluded, same for all)."""
+    import torch
+    import paper_2607_04489_amd as eg
+    import synth
+    dev = torch.device("cuda:0")
+    shapes = [(16, s_) for s_ in (16, 18, 20, 22, 24, 26, 28)] + [(r_, 28) for r_ in (20, 22, 24, 26)]
+    plans = {"hash": (eg.GLOBAL_HASH, 0, 0, 0.5), "radix": (eg.RADIX, 0, 0, 0.25), "sort_merge": (eg.SORT_MERGE, 0, 0, 0.0)}
+    cells = []
+    for dt_name, dt in (("int32", torch.int32), ("int64", torch.int64)):
+        for r_log, s_log in shapes:
+            inp = synth.wide_join(seed, 1 << r_log, 1 << s_log, 1000, n_cols=1, key_dtype=dt, col_dtype=dt, device=dev)
+            sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
+            cell = {"key": dt_name, "R_log2": r_log, "S_log2": s_log}
+            counts = set()
+            chosen = {k: eg.join_plan(sb, sp, eg.SEL_FORCED, eg.make_plan(*v)) for k, v in plans.items()}
+            chosen["rule"] = eg.join_plan(sb, sp, eg.SEL_RULE)
+            cell["rule_plan"] = chosen["rule"].describe()
+            for name, plan in chosen.items():
+                best = None
+                for r in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, plan)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3
+                    if r:
+                        best = ms if best is None else min(best, ms)
+                counts.add((res.count, res.checksum))
+                cell[name + "_ms"] = round(best, 3)
+                del res
+            cell["agree"] = len(counts) == 1
+            fastest = min(plans, key=lambda k: cell[k + "_ms"])
+            cell["fastest_fixed"] = fastest
+            cell["tuples_per_s_fastest"] = ((1 << r_log) + (1 << s_log)) / (cell[fastest + "_ms"] * 1e-3)
+            log(json.dumps(cell))
+            cells.append(cell)
+            del inp
+            torch.cuda.empty_cache()
+    return {"metric": "narrow join ms per plan (hash / partitioned hash / sort-merge / rule)", "cells": cells,
+            "workload": "unique build keys 2 * shuffle(|R|), every probe row copies a build key; one payload "
+                        "column per side of the key's width; throughput = (|R| + |S|) / time"}
+
+
 def host_cores():
     """Host CPUs this process may run on (the GPU machine grants 16)."""
     return max(1, min(16, len(os.sched_getaffinity(0))))
@@ -544,6 +594,9 @@ def main():
         return
     if args.workload == "groupby":
         print(json.dumps(bench_groupby(reps=max(1, args.steps))), flush=True)
+        return
+    if args.workload == "join_sweep":
+        print(json.dumps(bench_join_sweep(reps=max(1, args.steps))), flush=True)
         return
     if args.workload == "skf_sort":
         print(json.dumps(bench_skf_sort(reps=max(1, args.steps))), flush=True)

@@ -247,7 +247,15 @@ void fill_common(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *o
 
 void rule_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out) {
   const uint64_t range = key_range(b);
-  if (b.n > 0 && range <= kDirectMaxRange && range <= 4 * static_cast<uint64_t>(b.n)) {
+  // Duplicated build keys share a home slot, so open-addressing clusters grow
+  // with the copies of a key; those builds go to CSR runs (dense ranges) or to
+  // LDS tables after partitioning.
+  const bool duplicated = b.ndv < 0.9 * static_cast<double>(b.n);
+  // DIRECT only for duplicated keys: with distinct keys a hash slot holds key,
+  // row id and payload in one line, while a CSR probe reads three (offsets, row
+  // id, payload); measured 1.1-2.3x slower than GLOBAL_HASH on dense distinct
+  // builds of 2^16..2^26 rows
+  if (b.n > 0 && duplicated && range <= kDirectMaxRange && range <= 4 * static_cast<uint64_t>(b.n)) {
     out->variant = EIGER_DIRECT;
     out->load_factor = 0.f;
     return;
@@ -256,10 +264,12 @@ void rule_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *out
   // payload width is not part of the statistics: size the slot for 8-byte payloads
   const double slot = b.dtype == EIGER_INT64 ? 32.0 : 16.0;
   const double table = static_cast<double>(hash_slots(static_cast<uint64_t>(b.n), lf)) * slot;
-  // Duplicated build keys share a home slot, so open-addressing clusters grow
-  // with the copies of a key; those builds go to LDS tables after partitioning.
-  const bool duplicated = b.ndv < 0.9 * static_cast<double>(b.n);
-  if (table <= kHashTableBudget && (!duplicated || table <= 64.0 * 1024 * 1024)) {
+  // 16-byte slots (4-byte keys): the partitioned join overtakes the in-place
+  // probe above a 1 GiB table (2^24 distinct build rows, a 1 GiB table: 8.3 vs
+  // 8.2 ms; 2^26 rows, 4 GiB: 16.9 vs 12.3 ms, probe side 2^28 rows); 32-byte
+  // slots keep the in-place probe up to the whole budget
+  const double budget = b.dtype == EIGER_INT64 ? kHashTableBudget : kHashTableBudget / 4;
+  if (table <= budget && (!duplicated || table <= 64.0 * 1024 * 1024)) {
     out->variant = EIGER_GLOBAL_HASH;
     out->load_factor = lf;
     return;

@@ -49,11 +49,23 @@ def plan(b, p, sel=eg.SEL_RULE, forced=None):
     return eg.join_plan(b, p, sel, forced)
 
 
-def test_rule_plan_dense_range_is_direct(lib):
+def test_rule_plan_dense_range(lib):
+    # distinct keys in a dense range: the hash table (one line per probe) beats CSR runs
     p = plan(stats(65536, 0, 65535, 65536.0), stats(1 << 20, 0, 81919, 81920.0))
-    assert p.variant == eg.DIRECT
+    assert p.variant == eg.GLOBAL_HASH
     assert (p.build_min, p.build_max) == (0, 65535)
     assert p.predicted_out == (65536 * (1 << 20)) // 81920
+    # duplicated keys in a dense range: DIRECT's CSR runs
+    p = plan(stats(65536, 0, 16383, 16384.0), stats(1 << 20, 0, 16383, 16384.0))
+    assert p.variant == eg.DIRECT
+
+
+def test_rule_plan_int32_table_budget(lib):
+    # 2^24 distinct int32 keys: a 1 GiB table is probed in place; 2^25 (2 GiB): partitioned
+    p = plan(stats(1 << 24, 0, 1 << 30, float(1 << 24)), stats(1 << 28, 0, 1 << 30, float(1 << 24)))
+    assert p.variant == eg.GLOBAL_HASH
+    p = plan(stats(1 << 25, 0, 1 << 30, float(1 << 25)), stats(1 << 28, 0, 1 << 30, float(1 << 25)))
+    assert p.variant in (eg.RADIX, eg.RADIX_CACHE)
 
 
 def test_rule_plan_sparse_small_is_global_hash(lib):
