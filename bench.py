@@ -35,13 +35,15 @@ KERNEL_SOURCES = {
     "radix_hist": ["join_radix.hip", "common.hpp"],
     "cache_probe": ["join_radix.hip", "join_common.hpp", "common.hpp"],
     "stats_partial": ["stats.hip", "common.hpp"],
+    "sort_scatter": ["sort.hip", "sort.hpp", "common.hpp"],
+    "groupby_partition": ["groupby.hip", "common.hpp"],
 }
 # Kernel symbol fragments of each timed name (to find them in rocprofv3 output).
 KERNEL_SYMBOLS = {
     "hash_probe": "k_probe<eiger::(anonymous namespace)::HashTab", "hash_build": "k_hash_build",
     "direct_probe": "k_probe<eiger::(anonymous namespace)::DirectTab", "radix_scatter": "k_part_scatter",
     "radix_join": "k_radix_join", "radix_hist": "k_part_hist", "cache_probe": "k_cache_probe",
-    "stats_partial": "k_stats_partial",
+    "stats_partial": "k_stats_partial", "sort_scatter": "k_sort_scatter", "groupby_partition": "k_gb_partition",
 }
 
 
@@ -177,10 +179,14 @@ def kernel_bytes(plan, inp, count):
     return b
 
 
-def batch_bytes(nb, npr, lf=0.5):
+def batch_bytes(nb, npr, lf=0.5, radix_bits=0):
     """Device bytes one unique-key int32 join of a batch holds: its four input
     columns, its output range (one pair per probe row at most) and its table
-    region (16-byte slots, sized as the library sizes them for load factor lf)."""
+    region (16-byte slots, sized as the library sizes them for load factor lf),
+    or for a partitioned join its partitioned copies (key, payload, row id per
+    row and pass) and counters."""
+    if radix_bits:
+        return 8 * nb + 8 * npr + 8 * npr + 2 * 12 * (nb + npr) + (1 << 22)
     slots = 64
     while slots < nb / lf + 1.0:
         slots <<= 1
@@ -195,8 +201,8 @@ def batch_waves(sizes, budget, tune=None):
     import paper_2607_04489_amd as eg
     waves, cur, used = [], [], 0
     for j, (nb, npr) in enumerate(sizes):
-        lf = (tune or {}).get(eg.batch_bucket(nb), (0.5, 0))[0]
-        b = batch_bytes(nb, npr, lf)
+        t = tuple((tune or {}).get(eg.batch_bucket(nb), (0.5, 0, 0))) + (0,)
+        b = batch_bytes(nb, npr, t[0], t[2])
         if cur and used + b > budget:
             waves.append(cur)
             cur, used = [], 0
@@ -230,7 +236,7 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
         tune = batchmod.load()
     waves = batch_waves(sizes, budget, tune)
     graph_ms = rule_ms = fixed_ms = 0.0
-    pairs = direct = flagged = 0
+    pairs = direct = radix = flagged = 0
     agree = True
     for w, idx in enumerate(waves):
         inputs = [synth.batched_join(seed, j, log2_lo, log2_hi, device=dev) for j in idx]
@@ -274,6 +280,7 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
         agree = agree and all(r == (int(c), int(s_)) for r, c, s_ in zip(rres, counts, sums))
         pairs += int(counts.sum())
         direct += int((variants == eg.DIRECT).sum())
+        radix += int((variants == eg.RADIX).sum())
         flagged += int((flags != 0).sum())
         log(f"  wave {w}: {len(idx)} joins, graph {sum(times) / len(times):.2f} ms, per-join rule {t_rule:.1f} ms")
         del inputs, joins
@@ -287,7 +294,7 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
             "per_join_rule_ms": round(rule_ms, 3), "per_join_fixed_hash_ms": round(fixed_ms, 3),
             "speedup_vs_per_join_rule": round(rule_ms / graph_ms, 2),
             "speedup_vs_per_join_fixed_hash": round(fixed_ms / graph_ms, 2),
-            "direct_joins": direct, "flagged": flagged,
+            "direct_joins": direct, "radix_joins": radix, "flagged": flagged,
             "agrees_with_single_joins": bool(agree), "tuned": tune is not None,
             "workload": (f"{n_joins} unique-key int32 joins, build rows 2^U({log2_lo:g},{log2_hi:g}), probe 4-16x "
                          f"build, match U[0.1,1], half dense / half sparse keys; drawn and run in "
@@ -295,7 +302,7 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
 
 
 
-def bench_groupby(n_log2=28, reps=3, seed=42, groups_log2=(2, 6, 10, 14, 16, 18, 20, 22, 24, 26)):
+def bench_groupby(n_log2=28, reps=3, seed=42, groups_log2=(2, 6, 10, 14, 16, 18, 20, 22, 24, 26), dtypes=None):
     """Group-by at the paper's microbenchmark shape (Section 5.3: 2^28 rows, two
     aggregated columns, g groups): HASH, PARTITION and the HLL-guided choice
     ("auto", which includes the statistics pass) for 4-byte and 8-byte keys and
@@ -306,7 +313,7 @@ def bench_groupby(n_log2=28, reps=3, seed=42, groups_log2=(2, 6, 10, 14, 16, 18,
     dev = torch.device("cuda:0")
     n = 1 << n_log2
     rows = []
-    for dt in (torch.int32, torch.int64):
+    for dt in dtypes or (torch.int32, torch.int64):
         name = "int32" if dt == torch.int32 else "int64"
         ws_stats = torch.empty(eg.lib().eiger_stats_workspace_size(n, eg.column(torch.empty(0, dtype=dt)).dtype),
                                dtype=torch.uint8, device=dev)
@@ -583,6 +590,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-joins comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the rule-planner comparison of the learned plan")
     ap.add_argument("--autotune", action="store_true", help="autotune the batched graph before timing it")
+    ap.add_argument("--no-extras", action="store_true", help="skip the multi-key sort and group-by points")
+    ap.add_argument("--skf-config", default="", help="skf_sort: one configuration KEYSxDTYPE, e.g. 4xint32")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.workload, args.kernel,
@@ -599,7 +608,11 @@ def main():
         print(json.dumps(bench_join_sweep(reps=max(1, args.steps))), flush=True)
         return
     if args.workload == "skf_sort":
-        print(json.dumps(bench_skf_sort(reps=max(1, args.steps))), flush=True)
+        cfg = ((4, "int32"), (2, "int32"), (4, "int64"), (2, "int64"))
+        if args.skf_config:
+            k, d = args.skf_config.split("x")
+            cfg = ((int(k), d),)
+        print(json.dumps(bench_skf_sort(reps=max(1, args.steps), configs=cfg)), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -786,6 +799,18 @@ def main():
     if not args.no_ceilings:
         log("measuring the copy and random-read ceilings")
         out["ceilings"] = ceilings(dev)
+    if not args.no_extras and args.workload == "sparse_unique64":
+        # one point each of the operators beyond the single join, at the paper's shapes
+        del inp
+        torch.cuda.empty_cache()
+        log("multi-key sort (smart key fusion) and group-by points")
+        sk = bench_skf_sort(reps=2, configs=((4, "int32"),))["cells"][0]
+        gb = bench_groupby(reps=2, groups_log2=(4, 20), dtypes=(torch.int32,))["cells"]
+        out["other_operators"] = {
+            "skf_sort_4xint32_2p28": {k: sk[k] for k in ("ms", "rows_per_s", "total_bits", "sorted_ok")},
+            "groupby_int32_2p28": [{k: c[k] for k in ("groups_log2", "hash_ms", "partition_ms", "auto_ms",
+                                                      "auto_choice", "agree")} for c in gb],
+        }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.workload)

@@ -452,11 +452,16 @@ typedef struct {
 
 /* Knobs for the joins whose build side has 2^b .. 2^(b+1)-1 rows (bucket b). */
 typedef struct {
-    float load_factor;   /* hash-table occupancy, (0, 0.9]; default 0.5 */
+    float load_factor;   /* hash-table occupancy, (0, 0.9]; default 0.5 (RADIX: its LDS tables') */
     int32_t probe_tile;  /* probe rows per work item, 256..2^20; default 16384 */
+    int32_t radix_bits;  /* 0: the per-join table choice on the device (DIRECT or GLOBAL_HASH);
+                            1..16: the bucket's joins run the partitioned RADIX join inside the
+                            graph with 2^radix_bits partitions (two passes above 8 bits) */
 } eiger_batch_tune;
 #define EIGER_BATCH_BUCKETS 33
 #define EIGER_BATCH_DUPLICATE_BUILD 1u /* result flag: the join's build keys repeat */
+#define EIGER_BATCH_CAPACITY 2u        /* result flag: a RADIX join found more pairs than its
+                                          n_probe output slots (its pairs are incomplete) */
 
 /* Workspace bytes for a batch (tune: EIGER_BATCH_BUCKETS entries or NULL for defaults). */
 int eiger_join_batch_workspace_size(const eiger_batch_join *joins, int32_t n_joins, int32_t key_dtype,

@@ -795,6 +795,7 @@ def selector_loaded() -> bool:
 
 BATCH_BUCKETS = 33
 BATCH_DUPLICATE_BUILD = 1
+BATCH_CAPACITY = 2
 
 
 class BatchJoinT(ctypes.Structure):
@@ -804,7 +805,7 @@ class BatchJoinT(ctypes.Structure):
 
 
 class BatchTuneT(ctypes.Structure):
-    _fields_ = [("load_factor", ctypes.c_float), ("probe_tile", ctypes.c_int32)]
+    _fields_ = [("load_factor", ctypes.c_float), ("probe_tile", ctypes.c_int32), ("radix_bits", ctypes.c_int32)]
 
 
 def batch_bucket(n_build: int) -> int:
@@ -815,7 +816,9 @@ def batch_bucket(n_build: int) -> int:
 class Batch:
     """A captured batch of joins (eiger_join_batch_*). `joins` is a list of
     (build_keys, build_payload, probe_keys, probe_payload) device tensors; `tune`
-    maps bucket -> (load_factor, probe_tile). The tensors must outlive the batch."""
+    maps bucket -> (load_factor, probe_tile[, radix_bits]); radix_bits > 0 runs
+    the bucket's joins through the partitioned join inside the graph. The
+    tensors must outlive the batch."""
 
     def __init__(self, joins, tune=None, stream=None):
         import torch
@@ -838,8 +841,9 @@ class Batch:
         if tune:
             t = (BatchTuneT * BATCH_BUCKETS)()
             for b in range(BATCH_BUCKETS):
-                lf, tile = tune.get(b, (0.5, 16384))
-                t[b] = BatchTuneT(float(lf), int(tile))
+                v = tuple(tune.get(b, (0.5, 16384)))
+                lf, tile, bits = (v + (0,))[:3]
+                t[b] = BatchTuneT(float(lf), int(tile), int(bits))
             self._tune = t
         need = ctypes.c_size_t()
         _check(lib().eiger_join_batch_workspace_size(ctypes.byref(arr), len(joins), self.kdt, self.pdt,
@@ -882,8 +886,9 @@ class Batch:
 
     def resolve_flagged(self, flags, selector: int = SEL_RULE, stream=None) -> dict:
         """Joins the batch flagged (repeated build keys: the graph's first-match
-        probes do not hold for them) run again one by one through eiger_join with
-        the `selector` plan, which handles duplicates. Returns {join index:
+        probes do not hold for them; or a partitioned join with more pairs than
+        its output range) run again one by one through eiger_join with the
+        `selector` plan, which handles duplicates. Returns {join index:
         JoinResult}; the batch's own output ranges of those joins are not used."""
         out = {}
         for j in (int(x) for x in (flags != 0).nonzero()[0]):

@@ -1,6 +1,9 @@
 """Autotuner of the batched join graph: per size bucket (floor(log2 build rows)),
-pick the (load factor, probe tile) that makes that bucket's joins fastest, by
-timing graph launches of the bucket's joins alone for every candidate."""
+pick the (load factor, probe tile, radix bits) that makes that bucket's joins
+fastest, by timing graph launches of the bucket's joins alone for every
+candidate. radix bits 0 keeps the per-join table choice on the device (DIRECT
+or GLOBAL_HASH); > 0 runs the bucket through the partitioned join (fan-out
+2^bits) inside the graph."""
 from __future__ import annotations
 
 import json
@@ -12,7 +15,17 @@ import torch
 import paper_2607_04489_amd as eg
 
 TUNE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_tune.json")
-CANDIDATES = [(lf, tile) for lf in (0.25, 0.5) for tile in (4096, 16384, 65536)]
+CANDIDATES = [(lf, tile, 0) for lf in (0.25, 0.5) for tile in (4096, 16384, 65536)]
+RADIX_FROM_BUCKET = 14  # smaller joins: a partitioned join's ~20 launches outweigh its work
+
+
+def candidates_for(bucket, base=CANDIDATES):
+    """Hash/direct candidates, plus partitioned fan-outs around ~2^11 build rows
+    per partition for buckets of 2^14 build rows and more."""
+    out = list(base)
+    if bucket >= RADIX_FROM_BUCKET:
+        out += [(0.25, 16384, bits) for bits in sorted({max(1, min(16, bucket - d)) for d in (12, 11, 10)})]
+    return out
 
 
 def time_graph(joins, tune, reps=3):
@@ -31,32 +44,33 @@ def time_graph(joins, tune, reps=3):
     return best
 
 
-def autotune(joins, candidates=CANDIDATES, reps=3, log=print):
-    """joins: list of (bk, bp, pk, pp). Returns {bucket: (lf, tile)} and the timings."""
+def autotune(joins, candidates=None, reps=3, log=print):
+    """joins: list of (bk, bp, pk, pp). Returns {bucket: (lf, tile, bits)} and the timings."""
     by_bucket = {}
     for q in joins:
         by_bucket.setdefault(eg.batch_bucket(q[0].numel()), []).append(q)
     tune, table = {}, {}
     for b in sorted(by_bucket):
         times = {}
-        for lf, tile in candidates:
-            times[(lf, tile)] = time_graph(by_bucket[b], {b: (lf, tile)}, reps)
+        for c in (candidates or candidates_for(b)):
+            times[tuple(c)] = time_graph(by_bucket[b], {b: tuple(c)}, reps)
         best = min(times, key=times.get)
         tune[b] = best
-        table[b] = {f"{lf}/{tile}": round(t, 4) for (lf, tile), t in times.items()}
-        log(f"bucket 2^{b}: {len(by_bucket[b])} joins, best lf={best[0]} tile={best[1]} "
-            f"({times[best]:.3f} ms vs default {times.get((0.5, 16384), float('nan')):.3f} ms)")
+        table[b] = {f"{lf}/{tile}/{bits}": round(t, 4) for (lf, tile, bits), t in times.items()}
+        log(f"bucket 2^{b}: {len(by_bucket[b])} joins, best lf={best[0]} tile={best[1]} radix_bits={best[2]} "
+            f"({times[best]:.3f} ms vs default {times.get((0.5, 16384, 0), float('nan')):.3f} ms)")
     return tune, table
 
 
 def save(tune, path=TUNE_PATH, table=None):
     with open(path, "w") as f:
         json.dump({"format": "eiger-batch-tune-1",
-                   "buckets": {str(b): {"load_factor": lf, "probe_tile": tile} for b, (lf, tile) in tune.items()},
+                   "buckets": {str(b): {"load_factor": v[0], "probe_tile": v[1], "radix_bits": (tuple(v) + (0,))[2]}
+                               for b, v in tune.items()},
                    "timings_ms": {str(b): t for b, t in (table or {}).items()}}, f, indent=1)
 
 
 def load(path=TUNE_PATH):
     with open(path) as f:
         doc = json.load(f)
-    return {int(b): (v["load_factor"], v["probe_tile"]) for b, v in doc["buckets"].items()}
+    return {int(b): (v["load_factor"], v["probe_tile"], v.get("radix_bits", 0)) for b, v in doc["buckets"].items()}

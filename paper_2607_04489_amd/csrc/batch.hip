@@ -11,6 +11,10 @@
 //   unique    hash joins: every build row counts its key; more than one -> flag
 //   probe     probe tiles against their join's table, materialize pairs into
 //             the join's output range (first-match walks: build keys distinct)
+//   radix     joins of size buckets tuned to the partitioned join run the RADIX
+//             variant's own kernels (histograms, scans, scatters, LDS-table
+//             join) inside the same graph, one join after another, each into
+//             its own output range; a collect kernel copies their counters
 // Stages never wait on each other inside a kernel, so no workgroup spins.
 #include <algorithm>
 #include <vector>
@@ -26,7 +30,7 @@ constexpr uint32_t kBuildTile = 16384;
 constexpr int kBNT = 256;
 constexpr int kBIPT = 4;
 constexpr int kBSCAP = 4096;
-constexpr uint32_t kVarDirect = 0, kVarHash = 1;
+constexpr uint32_t kVarDirect = 0, kVarHash = 1, kVarRadix = 2;
 
 struct BatchJoinDev {
   const void *bk, *bp, *pk, *pp;
@@ -238,6 +242,16 @@ __global__ void __launch_bounds__(kBNT) k_batch_probe(const Item *__restrict__ i
   }
 }
 
+// Counters of a RADIX join run inside the graph -> its batch state.
+__global__ void k_batch_collect(const JoinCounters *__restrict__ c, BatchState *__restrict__ st, uint64_t cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->count = c->count;
+    st->checksum = c->checksum;
+    st->variant = kVarRadix;
+    st->flags = c->count > cap ? EIGER_BATCH_CAPACITY : 0u;
+  }
+}
+
 int bucket_of_rows(int64_t n) {
   int b = 0;
   while (b < EIGER_BATCH_BUCKETS - 1 && (int64_t(2) << b) <= n) ++b;
@@ -245,20 +259,30 @@ int bucket_of_rows(int64_t n) {
 }
 
 eiger_batch_tune tune_for(const eiger_batch_tune *tune, int64_t n) {
-  eiger_batch_tune t{0.5f, 16384};
+  eiger_batch_tune t{0.5f, 16384, 0};
   if (tune) {
     const eiger_batch_tune &u = tune[bucket_of_rows(n)];
     if (u.load_factor > 0.f && u.load_factor <= 0.9f) t.load_factor = u.load_factor;
     if (u.probe_tile >= 256 && u.probe_tile <= (1 << 20)) t.probe_tile = u.probe_tile;
+    if (u.radix_bits >= 1 && u.radix_bits <= 16) t.radix_bits = u.radix_bits;
   }
   return t;
 }
+
+// A join of the batch that runs the RADIX variant inside the graph.
+struct RadixJob {
+  int32_t join;
+  JoinArgs args;   // outputs and stream are filled in at capture
+  size_t ws_off, ws_bytes;
+};
 
 // Host-side description of a batch (descriptors, work items, sizes).
 struct BatchPlan {
   std::vector<BatchJoinDev> joins;
   std::vector<Item> build, probe;
+  std::vector<RadixJob> radix;
   uint64_t arena_slots = 0, out_total = 0;
+  size_t radix_ws = 0;
 };
 
 int plan_batch(const eiger_batch_join *joins, int32_t n, int32_t kdt, int32_t pdt, const eiger_batch_tune *tune,
@@ -279,6 +303,39 @@ int plan_batch(const eiger_batch_join *joins, int32_t n, int32_t kdt, int32_t pd
         reinterpret_cast<uintptr_t>(q.build_payload) % ps || reinterpret_cast<uintptr_t>(q.probe_payload) % ps)
       return fail(EIGER_ERR_INVALID_ARG, "batch: column not aligned to its dtype");
     const eiger_batch_tune t = tune_for(tune, q.n_build);
+    if (t.radix_bits > 0 && q.n_build > 0 && q.n_probe > 0) {
+      BatchJoinDev &d = bp->joins[j];
+      d = BatchJoinDev{q.build_keys, q.build_payload, q.probe_keys, q.probe_payload, uint64_t(q.n_build),
+                       uint64_t(q.n_probe), bp->out_total, bp->arena_slots, 0};
+      RadixJob job{};
+      job.join = j;
+      JoinArgs &a = job.args;
+      a.bk = q.build_keys;
+      a.bp = q.build_payload;
+      a.pk = q.probe_keys;
+      a.pp = q.probe_payload;
+      a.nR = uint64_t(q.n_build);
+      a.nS = uint64_t(q.n_probe);
+      a.kdt = kdt;
+      a.bpdt = pdt;
+      a.ppdt = pdt;
+      a.plan = eiger_plan_t{};
+      a.plan.variant = EIGER_RADIX;
+      a.plan.key_dtype = kdt;
+      a.plan.radix_bits = t.radix_bits;
+      a.plan.radix_passes = t.radix_bits > 8 ? 2 : 1;
+      a.plan.load_factor = t.load_factor;
+      a.cap = uint64_t(q.n_probe);
+      Workspace dry(nullptr, 0);
+      JoinCounters *unused = nullptr;
+      if (int rc = run_join_variant(a, dry, &unused)) return rc;
+      job.ws_off = bp->radix_ws;
+      job.ws_bytes = dry.used + 256;
+      bp->radix_ws += (job.ws_bytes + 255) & ~size_t(255);
+      bp->radix.push_back(job);
+      bp->out_total += uint64_t(q.n_probe);
+      continue;
+    }
     uint64_t slots = 64;
     const double want = static_cast<double>(q.n_build) / t.load_factor + 1.0;
     while (static_cast<double>(slots) < want) slots <<= 1;
@@ -304,6 +361,7 @@ struct BatchLayout {
   BatchState *state;
   Item *build, *probe;
   void *arena;
+  char *radix_ws;
 };
 
 BatchLayout batch_layout(Workspace &ws, const BatchPlan &bp, size_t slot_bytes_) {
@@ -313,6 +371,7 @@ BatchLayout batch_layout(Workspace &ws, const BatchPlan &bp, size_t slot_bytes_)
   L.build = ws.take<Item>(std::max<size_t>(bp.build.size(), 1));
   L.probe = ws.take<Item>(std::max<size_t>(bp.probe.size(), 1));
   L.arena = ws.take<char>(bp.arena_slots * slot_bytes_);
+  L.radix_ws = ws.take<char>(bp.radix_ws);
   return L;
 }
 
@@ -346,6 +405,17 @@ int enqueue_batch(const BatchPlan &bp, const BatchLayout &L, uint32_t *ob, uint3
   if (np) {
     EIGER_LAUNCH("batch_probe", (k_batch_probe<K, P>), dim3(std::min(np, cus * 4)), dim3(kBNT), 0, s, L.probe, np,
                  L.joins, L.state, static_cast<const Slot<K, P> *>(L.arena), ob, op);
+  }
+  for (const RadixJob &job : bp.radix) {
+    JoinArgs a = job.args;
+    const uint64_t off = bp.joins[job.join].out_off;
+    a.ob = ob + off;
+    a.op = op + off;
+    a.s = s;
+    Workspace w(L.radix_ws + job.ws_off, job.ws_bytes);
+    JoinCounters *c = nullptr;
+    if ((rc = run_join_variant(a, w, &c))) return rc;
+    EIGER_LAUNCH("batch_collect", k_batch_collect, dim3(1), dim3(64), 0, s, c, L.state + job.join, a.cap);
   }
   return EIGER_OK;
 }
@@ -452,7 +522,10 @@ extern "C" int eiger_join_batch_results(void *handle, int64_t *counts, int64_t *
   for (int j = 0; j < h->n; ++j) {
     if (counts) counts[j] = static_cast<int64_t>(st[j].count);
     if (checksums) checksums[j] = static_cast<int64_t>(st[j].checksum);
-    if (variants) variants[j] = st[j].variant == kVarDirect ? EIGER_DIRECT : EIGER_GLOBAL_HASH;
+    if (variants)
+      variants[j] = st[j].variant == kVarDirect ? EIGER_DIRECT
+                    : st[j].variant == kVarRadix ? EIGER_RADIX
+                                                 : EIGER_GLOBAL_HASH;
     if (flags) flags[j] = st[j].flags;
   }
   return EIGER_OK;

@@ -161,3 +161,50 @@ def test_batch_spec_shape_in_waves(gpu):
         del inputs
         torch.cuda.empty_cache()
     assert checked == 64
+
+
+def test_batch_partitioned_buckets_match_oracle(gpu):
+    """Size buckets tuned to the partitioned join run RADIX inside the graph
+    (next to hash and direct joins of other buckets): pairs, counts and
+    checksums equal the oracle's, duplicated build keys included (RADIX joins
+    them natively, no flag), and a join with more pairs than probe rows is
+    flagged for capacity and resolved through eiger_join."""
+    inputs = synth.batched_joins(12, 48, log2_lo=6.0, log2_hi=16.0, device=gpu)
+    dup = 3 if inputs[3].n_build >= 1024 else max(range(48), key=lambda j: inputs[j].n_build)
+    bk = inputs[dup].build_keys.clone()
+    bk[1::7] = bk[0]
+    inputs[dup] = synth.JoinInput("dups", bk, inputs[dup].build_payload, inputs[dup].probe_keys,
+                                  inputs[dup].probe_payload)
+    # all probe rows of one join carry the repeated key: more pairs than probe rows
+    over = max((j for j in range(48) if j != dup), key=lambda j: inputs[j].n_build)
+    obk = inputs[over].build_keys.clone()
+    obk[:4] = obk[0]
+    opk = torch.full_like(inputs[over].probe_keys, int(obk[0]))
+    inputs[over] = synth.JoinInput("over", obk, inputs[over].build_payload, opk, inputs[over].probe_payload)
+    tune = {b: (0.25, 4096, max(1, b - 10)) for b in range(10, 33)}
+    b = eg.Batch([as_tuple(i) for i in inputs], tune)
+    b.launch()
+    counts, sums, variants, flags = b.results()
+    radix = [j for j, i in enumerate(inputs) if i.n_build >= 1024 and i.n_probe > 0]
+    assert len(radix) >= 8 and all(variants[j] == eg.RADIX for j in radix)
+    assert dup in radix and over in radix
+    for j, inp in enumerate(inputs):
+        pairs, cnt, cs = oracle.join_sortmerge(*as_tuple(inp))
+        assert (counts[j], sums[j]) == (cnt, cs), j
+        if j == over:
+            assert flags[j] == eg.BATCH_CAPACITY
+            continue
+        assert flags[j] == 0, j
+        ob, op = b.pairs(j, cnt)
+        got = oracle.canonical_pairs(ob.cpu().numpy().view(np.uint32), op.cpu().numpy().view(np.uint32))
+        assert np.array_equal(got, pairs), j
+    fixed = b.resolve_flagged(flags)
+    assert sorted(fixed) == [over]
+    pairs, cnt, cs = oracle.join_sortmerge(*as_tuple(inputs[over]))
+    got = oracle.canonical_pairs(fixed[over].build_rowid.cpu().numpy().view(np.uint32),
+                                 fixed[over].probe_rowid.cpu().numpy().view(np.uint32))
+    assert np.array_equal(got, pairs)
+    # replays give the same results
+    b.launch()
+    again = b.results()
+    assert all(np.array_equal(a, c) for a, c in zip((counts, sums, variants, flags), again))
