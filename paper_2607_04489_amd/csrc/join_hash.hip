@@ -5,10 +5,15 @@
 // 16-byte slot (32 bytes when key and payload are both 8 bytes), so a probe
 // touches one cache line per slot group instead of gathering keys through
 // tuple ids (the cost the paper blames for the hash join's losses, Section
-// 5.2.1). Slots are claimed by CAS on the row-id word (empty = 0xFFFFFFFF), so
-// no key value is reserved as a sentinel. The table is a multiset: duplicate
-// build keys occupy several slots and a probe walks the whole cluster (linear
-// probing) until an empty slot.
+// 5.2.1). Slots are claimed by CAS on the key word with a sentinel key outside
+// the build range (duplicates show up during the build), or, when the build
+// keys reach both ends of the key domain, by CAS on the row-id word followed
+// by a duplicate check. Empty slots have row id 0xFFFFFFFF either way. The
+// table is a multiset: duplicate build keys occupy several slots and a probe
+// walks the whole cluster (linear probing) until an empty slot.
+#include <limits>
+#include <type_traits>
+
 #include "join_common.hpp"
 #include "variants.hpp"
 
@@ -84,6 +89,67 @@ __global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ 
   }
 }
 
+// Table clear for the key-claiming build: key = sentinel, row id = empty.
+template <typename K, typename PB>
+__global__ void __launch_bounds__(256) k_hash_clear(Slot<K, PB> *__restrict__ slots, uint64_t n, K sentinel) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  Slot<K, PB> e{};
+  e.key = sentinel;
+  e.rowid = kEmpty;
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) slots[i] = e;
+}
+
+// Build that claims a slot by CAS on its key word (empty = a sentinel value no
+// build key takes), so a row that meets its own key on the way has found a
+// duplicate: the distinctness flag comes out of the build, without a second
+// walk per build row. A key equal to the sentinel (the plan's key range was
+// wrong) is reported through the counters' flags.
+template <typename K, typename PB>
+__global__ void k_hash_build_keys(const K *__restrict__ keys, const PB *__restrict__ pay, uint64_t n,
+                                  Slot<K, PB> *__restrict__ slots, uint64_t mask, K sentinel, uint32_t *dup,
+                                  uint64_t *flags) {
+  using W = typename std::conditional<sizeof(K) == 8, unsigned long long, unsigned int>::type;
+  const W empty = static_cast<W>(sentinel);
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  bool seen = false;
+  for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const K key = keys[r];
+    if (key == sentinel) {
+      atomicOr(reinterpret_cast<unsigned long long *>(flags), kFlagBuildOutOfRange);
+      continue;
+    }
+    uint64_t i = fmix64(static_cast<uint64_t>(sext(key))) & mask;
+    // The table has more slots than rows, so an empty slot is always found.
+    for (;;) {
+      const W old = atomicCAS(reinterpret_cast<W *>(&slots[i].key), empty, static_cast<W>(key));
+      if (old == empty) {
+        slots[i].rowid = static_cast<uint32_t>(r);
+        slots[i].pay = pay[r];
+        break;
+      }
+      seen |= old == static_cast<W>(key);
+      i = (i + 1) & mask;
+    }
+  }
+  if (seen) atomicOr(dup, 1u);
+}
+
+// A key value outside the plan's build range, if the key type has one.
+template <typename K>
+bool hash_sentinel(const JoinArgs &a, K *out) {
+  const int64_t lo = static_cast<int64_t>(std::numeric_limits<K>::min());
+  const int64_t hi = static_cast<int64_t>(std::numeric_limits<K>::max());
+  if (a.nR == 0 || a.plan.build_min > lo) {
+    *out = std::numeric_limits<K>::min();
+    return true;
+  }
+  if (a.plan.build_max < hi) {
+    *out = std::numeric_limits<K>::max();
+    return true;
+  }
+  return false;
+}
+
 // Each workgroup streams a contiguous range of probe rows (an equal share of
 // whole sub-tiles).
 template <class Tab, typename K, typename PS>
@@ -123,13 +189,23 @@ int hash_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   if ((rc = fill_u64(reinterpret_cast<uint64_t *>(c), 4, 0, s))) return rc;
   if (a.nR == 0 || a.nS == 0) return EIGER_OK;
   if ((rc = fill_u32(dup, 1, 0, s))) return rc;
-  if ((rc = fill_u32(reinterpret_cast<uint32_t *>(slots), nslots * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
-    return rc;
-  EIGER_LAUNCH("hash_build", (k_hash_build<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
-               static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1);
   HashTab<K, PB> tab{slots, nslots - 1, dup, false};
-  EIGER_LAUNCH("hash_unique", (k_hash_unique<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
-               static_cast<const K *>(a.bk), a.nR, tab, dup);
+  K sentinel;
+  if (hash_sentinel<K>(a, &sentinel)) {
+    EIGER_LAUNCH("hash_clear", (k_hash_clear<K, PB>), dim3(grid_for(nslots, 256 * 4, 8)), dim3(256), 0, s, slots,
+                 nslots, sentinel);
+    EIGER_LAUNCH("hash_build", (k_hash_build_keys<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
+                 static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1, sentinel,
+                 dup, &c->flags);
+  } else {
+    // keys at both ends of the domain: claim by row id, then a duplicate check
+    if ((rc = fill_u32(reinterpret_cast<uint32_t *>(slots), nslots * sizeof(Slot<K, PB>) / 4, kEmpty, s)))
+      return rc;
+    EIGER_LAUNCH("hash_build", (k_hash_build<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
+                 static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1);
+    EIGER_LAUNCH("hash_unique", (k_hash_unique<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
+                 static_cast<const K *>(a.bk), a.nR, tab, dup);
+  }
   EmitOut o{a.ob, a.op, a.cap, &c->count, &c->checksum};
   EIGER_LAUNCH("hash_probe", (k_probe<HashTab<K, PB>, K, PS>),
                dim3(grid_for(a.nS, uint64_t(kNT) * kIPT, 4)), dim3(kNT), 0, s, tab,

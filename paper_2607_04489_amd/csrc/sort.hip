@@ -25,10 +25,19 @@ constexpr int kSDigitBits = 8;
 constexpr int kSDigits = 1 << kSDigitBits;
 static_assert(kSDigits == kSNT, "one thread per digit in the per-tile digit scan");
 
+// Tiles of 8,192 items (4,096 for 8-byte keys): each digit's run of a tile
+// averages 32 items, so its writes cover whole 128-byte lines more often
+// (measured per 4-byte pass at 2^28 items: 2,048 items 3.8 ms, 4,096 2.7 ms,
+// 6,144 1.9 ms, 8,192 1.7 ms).
 template <typename K>
 constexpr int items_per_thread() {
-  return sizeof(K) == 8 ? 8 : 16;
+  return sizeof(K) == 8 ? 16 : 32;
 }
+// Workgroups per CU of the grids; workgroups loop over the remaining tiles. The
+// histogram keeps one tile per workgroup; the scatter, whose workgroups hold
+// 70 KB of LDS, runs best with a few resident workgroups per CU.
+constexpr uint64_t kHistPerCu = 64;
+constexpr uint64_t kScatPerCu = 8;
 
 template <typename K>
 constexpr int tile_items() {
@@ -40,21 +49,26 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift, uint32_t mask) {
   return static_cast<uint32_t>(k >> shift) & mask;
 }
 
+// Workgroups loop over tiles (the grid is sized to the chip): one workgroup
+// per tile was limited by how fast workgroups are dispatched, not by memory.
 template <typename K>
 __global__ void __launch_bounds__(kSNT) k_sort_hist(const K *__restrict__ keys, uint64_t n, int shift,
                                                     uint32_t mask, uint32_t ntiles, uint32_t *__restrict__ cnt) {
   constexpr int kItems = items_per_thread<K>();
   __shared__ uint32_t h[kSDigits];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * tile_items<K>();
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(tile) * tile_items<K>();
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint64_t i = base + static_cast<uint64_t>(j) * kSNT + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t i = base + static_cast<uint64_t>(j) * kSNT + threadIdx.x;
+      if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x <= mask) cnt[static_cast<uint64_t>(threadIdx.x) * ntiles + tile] = h[threadIdx.x];
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x <= mask) cnt[static_cast<uint64_t>(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
 // vin == nullptr: the values are the row ids (first pass of a permutation sort).
@@ -74,75 +88,78 @@ __global__ void __launch_bounds__(kSNT) k_sort_scatter(const K *__restrict__ kin
   const uint32_t mask = (1u << bits) - 1u;
   const int lane = __lane_id();
   const int w = threadIdx.x / 64;
+  for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
 #pragma unroll
-  for (int x = 0; x < kSWaves; ++x) wcnt[x][threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t base = static_cast<uint64_t>(blockIdx.x) * T;
-  const uint64_t wbase = base + static_cast<uint64_t>(w) * (64 * kItems);
-  K key[kItems];
-  uint32_t val[kItems], lo[kItems];
+    for (int x = 0; x < kSWaves; ++x) wcnt[x][threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(tile) * T;
+    const uint64_t wbase = base + static_cast<uint64_t>(w) * (64 * kItems);
+    K key[kItems];
+    uint32_t val[kItems], lo[kItems];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
-    const bool ok = i < n;
-    key[j] = ok ? kin[i] : K(0);
-    val[j] = ok ? (vin ? vin[i] : static_cast<uint32_t>(i)) : 0u;
-  }
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
+      const bool ok = i < n;
+      key[j] = ok ? kin[i] : K(0);
+      val[j] = ok ? (vin ? vin[i] : static_cast<uint32_t>(i)) : 0u;
+    }
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
-    const bool ok = i < n;
-    const uint32_t d = digit_of(key[j], shift, mask);
-    uint64_t peers = __ballot(ok);
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
+      const bool ok = i < n;
+      const uint32_t d = digit_of(key[j], shift, mask);
+      uint64_t peers = __ballot(ok);
 #pragma unroll
-    for (int b = 0; b < kSDigitBits; ++b) {
-      if (b < bits) {
-        const bool set = (d >> b) & 1u;
-        const uint64_t bb = __ballot(set);
-        peers &= set ? bb : ~bb;
+      for (int b = 0; b < kSDigitBits; ++b) {
+        if (b < bits) {
+          const bool set = (d >> b) & 1u;
+          const uint64_t bb = __ballot(set);
+          peers &= set ? bb : ~bb;
+        }
+      }
+      const uint32_t before = lane_prefix(peers);
+      // every lane reads the wave's running count before the group's first lane
+      // (the only writer of this digit in this step) stores the new one; LDS
+      // operations of one wave complete in order
+      const uint32_t pre = ok ? wcnt[w][d] : 0u;
+      if (ok && before == 0) wcnt[w][d] = pre + static_cast<uint32_t>(__popcll(peers));
+      lo[j] = pre + before;
+    }
+    __syncthreads();
+    // digit t: exclusive prefix over the waves (wave order = item order), tile total
+    const int t = threadIdx.x;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int x = 0; x < kSWaves; ++x) {
+      const uint32_t c = wcnt[x][t];
+      wcnt[x][t] = tot;
+      tot += c;
+    }
+    uint32_t all;
+    const uint32_t ds = block_exclusive_scan<kSNT, uint32_t>(tot, scan_tmp, &all);
+    dstart[t] = ds;
+    // global start of this tile's run of digit t, minus its start inside the tile
+    adj[t] = static_cast<uint32_t>(t) <= mask ? offs[static_cast<uint64_t>(t) * ntiles + tile] - ds : 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
+      if (i < n) {
+        const uint32_t d = digit_of(key[j], shift, mask);
+        const uint32_t p = dstart[d] + wcnt[w][d] + lo[j];
+        sk[p] = key[j];
+        sv[p] = val[j];
       }
     }
-    const uint32_t before = lane_prefix(peers);
-    // every lane reads the wave's running count before the group's first lane
-    // (the only writer of this digit in this step) stores the new one; LDS
-    // operations of one wave complete in order
-    const uint32_t pre = ok ? wcnt[w][d] : 0u;
-    if (ok && before == 0) wcnt[w][d] = pre + static_cast<uint32_t>(__popcll(peers));
-    lo[j] = pre + before;
-  }
-  __syncthreads();
-  // digit t: exclusive prefix over the waves (wave order = item order), tile total
-  const int t = threadIdx.x;
-  uint32_t tot = 0;
-#pragma unroll
-  for (int x = 0; x < kSWaves; ++x) {
-    const uint32_t c = wcnt[x][t];
-    wcnt[x][t] = tot;
-    tot += c;
-  }
-  uint32_t all;
-  const uint32_t ds = block_exclusive_scan<kSNT, uint32_t>(tot, scan_tmp, &all);
-  dstart[t] = ds;
-  // global start of this tile's run of digit t, minus its start inside the tile
-  adj[t] = static_cast<uint32_t>(t) <= mask ? offs[static_cast<uint64_t>(t) * ntiles + blockIdx.x] - ds : 0u;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
-    if (i < n) {
-      const uint32_t d = digit_of(key[j], shift, mask);
-      const uint32_t p = dstart[d] + wcnt[w][d] + lo[j];
-      sk[p] = key[j];
-      sv[p] = val[j];
+    __syncthreads();
+    const uint32_t in_tile = static_cast<uint32_t>(min<uint64_t>(T, n - base));
+    for (uint32_t p = threadIdx.x; p < in_tile; p += kSNT) {
+      const K k = sk[p];
+      const uint32_t o = adj[digit_of(k, shift, mask)] + p;
+      kout[o] = k;
+      vout[o] = sv[p];
     }
-  }
-  __syncthreads();
-  const uint32_t in_tile = static_cast<uint32_t>(min<uint64_t>(T, n - base));
-  for (uint32_t p = threadIdx.x; p < in_tile; p += kSNT) {
-    const K k = sk[p];
-    const uint32_t o = adj[digit_of(k, shift, mask)] + p;
-    kout[o] = k;
-    vout[o] = sv[p];
+    __syncthreads();
   }
 }
 
@@ -175,6 +192,8 @@ int sort_impl(const K *kin, const uint32_t *vin, uint64_t n, int key_bits, K *ko
     return EIGER_OK;
   }
   // balanced digit widths, least significant digit first; the last pass lands in out
+  const unsigned hist_grid = static_cast<unsigned>(std::min<uint64_t>(ntiles, uint64_t(device_cu_count()) * kHistPerCu));
+  const unsigned scat_grid = static_cast<unsigned>(std::min<uint64_t>(ntiles, uint64_t(device_cu_count()) * kScatPerCu));
   int shift = 0;
   const K *src_k = kin;
   const uint32_t *src_v = vin;
@@ -184,11 +203,11 @@ int sort_impl(const K *kin, const uint32_t *vin, uint64_t n, int key_bits, K *ko
     K *dk = to_out ? kout : k2;
     uint32_t *dv = to_out ? vout : v2;
     const uint32_t mask = (1u << bits) - 1u;
-    EIGER_LAUNCH("sort_hist", k_sort_hist<K>, dim3(static_cast<unsigned>(ntiles)), dim3(kSNT), 0, s, src_k, n,
+    EIGER_LAUNCH("sort_hist", k_sort_hist<K>, dim3(hist_grid), dim3(kSNT), 0, s, src_k, n,
                  shift, mask, static_cast<uint32_t>(ntiles), cnt);
     int rc = exclusive_scan_u32(cnt, cnt, (static_cast<uint64_t>(mask) + 1) * ntiles, tmp, total, s);
     if (rc) return rc;
-    EIGER_LAUNCH("sort_scatter", k_sort_scatter<K>, dim3(static_cast<unsigned>(ntiles)), dim3(kSNT), 0, s, src_k,
+    EIGER_LAUNCH("sort_scatter", k_sort_scatter<K>, dim3(scat_grid), dim3(kSNT), 0, s, src_k,
                  src_v, n, shift, bits, static_cast<uint32_t>(ntiles), cnt, dk, dv);
     src_k = dk;
     src_v = dv;
