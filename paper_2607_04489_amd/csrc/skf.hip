@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kDeNT) k_de_insert(Rows<K> rows, DeTable t, ui
       }
       if (slot == t.mask + 2) t.ctr[2] = 1u;
     }
-    if (loc) loc[i] = static_cast<uint32_t>(slot);
+    loc[i] = static_cast<uint32_t>(slot);
   }
 }
 
@@ -136,9 +136,8 @@ __global__ void __launch_bounds__(kDeNT) k_de_dict(const unsigned long long *__r
 struct FuseKey {
   const void *a;
   const void *b;
-  const unsigned long long *table;  // DICT: the encoding's hash table (key per slot)
-  uint64_t mask;                    // DICT: slots - 1
-  const uint32_t *code_of_slot;     // DICT: code of each slot
+  const uint32_t *loc;           // DICT: slot of each row
+  const uint32_t *code_of_slot;  // DICT: code of each slot
   uint64_t base;                 // FOR: minimum (two's-complement bits)
   uint64_t flip;                 // all-ones over the width for a descending key, else 0
   int32_t wide;                  // 8-byte key column
@@ -169,41 +168,11 @@ __global__ void __launch_bounds__(kDeNT) k_skf_fuse(FuseArgs A) {
       if (k.bits == 0) continue;
       uint64_t code[kDeBatch];
       if (k.dict) {
-        // step 5 by looking the key up again in its table (every key was
-        // inserted, within the insert's probe bound of its home slot), rather
-        // than storing a slot id per row during the insert and reading it here
-        unsigned long long key[kDeBatch], cur[kDeBatch];
-        uint64_t h[kDeBatch];
-#pragma unroll
-        for (int b = 0; b < kDeBatch; ++b) {
-          const uint64_t i = base + uint64_t(b) * kDeNT;
-          key[b] = kDeEmpty;
-          if (i < A.n) {
-            const void *p = i < A.na ? k.a : k.b;
-            const uint64_t j = i < A.na ? i : i - A.na;
-            key[b] = k.wide ? static_cast<unsigned long long>(static_cast<const int64_t *>(p)[j])
-                            : static_cast<unsigned long long>(static_cast<int64_t>(static_cast<const int32_t *>(p)[j]));
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < kDeBatch; ++b) {
-          h[b] = fmix64(key[b]) & k.mask;
-          cur[b] = key[b] != kDeEmpty ? k.table[h[b]] : kDeEmpty;
-        }
         uint32_t sl[kDeBatch];
 #pragma unroll
         for (int b = 0; b < kDeBatch; ++b) {
-          if (key[b] == kDeEmpty) {
-            sl[b] = static_cast<uint32_t>(k.mask + 1);
-            continue;
-          }
-          uint64_t hh = h[b];
-          unsigned long long c = cur[b];
-          for (uint64_t probe = 1; c != key[b] && probe < kDeMaxProbe; ++probe) {
-            hh = (hh + 1) & k.mask;
-            c = k.table[hh];
-          }
-          sl[b] = static_cast<uint32_t>(hh);
+          const uint64_t i = base + uint64_t(b) * kDeNT;
+          sl[b] = i < A.n ? k.loc[i] : 0u;
         }
 #pragma unroll
         for (int b = 0; b < kDeBatch; ++b) {
@@ -337,9 +306,7 @@ size_t sort_ws_bytes(int key_bytes, uint64_t n, int bits) {
   return w.used + 256;
 }
 
-// with_loc: keep each row's slot id (the stand-alone encoding gathers codes through it;
-// fusion looks keys up in the table instead)
-size_t skf_layout(Workspace &ws, const eiger_skf_plan_t &p, uint64_t n, bool sort, bool with_loc, SkfLayout *L) {
+size_t skf_layout(Workspace &ws, const eiger_skf_plan_t &p, uint64_t n, bool sort, SkfLayout *L) {
   *L = SkfLayout{};
   L->ctr = ws.take<uint32_t>(4 * EIGER_SKF_MAX_KEYS);
   uint64_t max_slots = 0;
@@ -351,7 +318,7 @@ size_t skf_layout(Workspace &ws, const eiger_skf_plan_t &p, uint64_t n, bool sor
     d.t.key = ws.take<unsigned long long>(slots);
     d.t.mask = slots - 1;
     d.t.ctr = L->ctr ? L->ctr + 4 * c : nullptr;
-    d.loc = with_loc ? ws.take<uint32_t>(n) : nullptr;
+    d.loc = ws.take<uint32_t>(n);
     d.ukey = ws.take<unsigned long long>(slots + 1);
     d.skey = ws.take<unsigned long long>(slots + 1);
     d.uslot = ws.take<uint32_t>(slots + 1);
@@ -438,8 +405,7 @@ int launch_fuse(const eiger_skf_plan_t &p, const eiger_column *ka, const eiger_c
     f.b = kb ? kb[c].data : nullptr;
     f.wide = k.dtype == EIGER_INT64;
     f.dict = k.code == EIGER_SKF_DICT;
-    f.table = L.d[c].t.key;
-    f.mask = L.d[c].t.mask;
+    f.loc = L.d[c].loc;
     f.code_of_slot = L.d[c].code_of_slot;
     f.base = static_cast<uint64_t>(k.base);
     f.bits = k.bits;
@@ -468,10 +434,10 @@ int check_keys(const eiger_column *keys, int32_t n_keys, const eiger_skf_plan_t 
   return EIGER_OK;
 }
 
-size_t skf_total_bytes(const eiger_skf_plan_t &p, uint64_t n, bool sort, bool with_loc = false) {
+size_t skf_total_bytes(const eiger_skf_plan_t &p, uint64_t n, bool sort) {
   Workspace ws(nullptr, 0);
   SkfLayout L;
-  const size_t sort_need = skf_layout(ws, p, n, sort, with_loc, &L);
+  const size_t sort_need = skf_layout(ws, p, n, sort, &L);
   ws.take<char>(sort_need);
   return ws.used + 256;
 }
@@ -496,7 +462,7 @@ int skf_run(const eiger_column *ka, const eiger_column *kb, int32_t n_keys, cons
   if (n > 0 && !wsp) return fail(EIGER_ERR_INVALID_ARG, std::string(who) + ": NULL workspace");
   Workspace ws(wsp, ws_bytes);
   SkfLayout L;
-  const size_t sort_need = skf_layout(ws, *plan, n, sort, false, &L);
+  const size_t sort_need = skf_layout(ws, *plan, n, sort, &L);
   void *sort_ws = ws.take<char>(sort_need);
   int rc = dict_steps(*plan, ka, kb, static_cast<uint64_t>(na), n, L, sort_ws, sort_need, out_plan, s);
   if (rc) return rc;
@@ -592,7 +558,7 @@ extern "C" int eiger_dict_encode_workspace_size(eiger_column col, int64_t slots,
   p.key[0].slots = slots;
   p.key[0].range_bits = 64;
   if (int rc = check_plan(&p, "eiger_dict_encode")) return rc;
-  *bytes = skf_total_bytes(p, static_cast<uint64_t>(col.n), false, true);
+  *bytes = skf_total_bytes(p, static_cast<uint64_t>(col.n), false);
   return EIGER_OK;
 }
 
@@ -615,7 +581,7 @@ extern "C" int eiger_dict_encode(eiger_column col, int64_t slots, uint32_t *out_
   if (col.n == 0) return EIGER_OK;
   Workspace ws(wsp, ws_bytes);
   SkfLayout L;
-  const size_t sort_need = skf_layout(ws, p, static_cast<uint64_t>(col.n), false, true, &L);
+  const size_t sort_need = skf_layout(ws, p, static_cast<uint64_t>(col.n), false, &L);
   void *sort_ws = ws.take<char>(sort_need);
   eiger_skf_plan_t fin;
   int rc = dict_steps(p, &col, nullptr, static_cast<uint64_t>(col.n), static_cast<uint64_t>(col.n), L, sort_ws,

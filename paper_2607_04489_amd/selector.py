@@ -253,3 +253,51 @@ def load_model(path=MODEL_PATH, install=True):
     if install:
         eg.selector_load(model["params"], model["mean"], model["std"], model["lo"], model["hi"])
     return model
+
+
+# The three instance families of the training data: collect() arguments.
+FAMILIES = {
+    1: dict(n_instances=4000, seed=7),
+    2: dict(n_instances=771, seed=8, family=2, min_build_log2=16.0, max_build_log2=26.0, max_probe_log2=28.0),
+    3: dict(n_instances=243, seed=9, family=3, min_build_log2=22.0, max_build_log2=28.0, max_probe_log2=29.0),
+}
+FAMILY_PATHS = {1: DATA_PATH, 2: DATA_PATH_WIDE, 3: DATA_PATH_LARGE}
+
+
+def main(argv=None):
+    """python -m paper_2607_04489_amd.selector collect --family F [--out PATH] [--time-limit S]
+       python -m paper_2607_04489_amd.selector train [--out MODEL]
+    collect resumes a partial file; train fits on the 80% split of every data
+    file and prints the held-out evaluation."""
+    import argparse
+    ap = argparse.ArgumentParser(prog="paper_2607_04489_amd.selector")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--family", type=int, choices=sorted(FAMILIES), required=True)
+    c.add_argument("--out", default=None)
+    c.add_argument("--time-limit", type=float, default=None)
+    t = sub.add_parser("train")
+    t.add_argument("--out", default=MODEL_PATH)
+    t.add_argument("--steps", type=int, default=2000)
+    args = ap.parse_args(argv)
+    if args.cmd == "collect":
+        kw = dict(FAMILIES[args.family])
+        n = kw.pop("n_instances")
+        collect(args.out or FAMILY_PATHS[args.family], n, time_limit_s=args.time_limit, log_every=10, **kw)
+        return
+    recs = load_records()
+    train_set, test_set = split(recs, seed=0)
+    model = train(train_set, steps=args.steps, lr=3e-3, seed=0)
+    ev = evaluate(model, test_set)
+    by_family = {}
+    for f in sorted(FAMILIES):
+        part = [r for r in test_set if r.get("params", {}).get("family", 1) == f]
+        if part:
+            by_family[f"family{f}"] = evaluate(model, part)
+    save_model(model, args.out, extra={"eval_holdout": ev, "eval_holdout_by_family": by_family,
+                                       "records": len(recs)})
+    print(json.dumps({"eval_holdout": ev, "eval_holdout_by_family": by_family}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
