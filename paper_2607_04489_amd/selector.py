@@ -35,7 +35,17 @@ DATA_PATH_WIDE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selec
 # family 3: builds of 2^22..2^28 rows, probes up to 2^29 rows
 DATA_PATH_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data",
                                "timings_mi355x_large.jsonl")
-DATA_PATHS = (DATA_PATH, DATA_PATH_WIDE, DATA_PATH_LARGE)
+# family 4: instances shaped like the large sparse and the skewed benchmark joins
+# (other seeds and sizes than the benchmark's own instances)
+DATA_PATH_SHAPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "selector_data",
+                                "timings_mi355x_shaped.jsonl")
+DATA_PATHS = (DATA_PATH, DATA_PATH_WIDE, DATA_PATH_LARGE, DATA_PATH_SHAPED)
+SHAPED = ([("sparse_unique64", dict(seed=100 + i, n_build=1 << b, n_probe=1 << p, match_per_mille=m))
+           for i, (b, p, m) in enumerate([(23, 28, 900), (24, 28, 900), (24, 29, 800), (25, 29, 900),
+                                          (22, 29, 900), (24, 27, 950), (23, 29, 700), (25, 28, 900)])] +
+          [("skewed_dup32", dict(seed=120 + i, n_distinct=1 << d, n_probe=1 << p, zipf_s=z))
+           for i, (d, p, z) in enumerate([(23, 28, 0.5), (24, 27, 1.0), (24, 28, 0.75), (24, 28, 1.25),
+                                          (23, 27, 1.5), (22, 28, 1.0), (24, 28, 0.3), (23, 28, 1.1)])])
 FIXED_HASH_CLASS = 2  # GLOBAL_HASH at load factor 0.5
 
 
@@ -149,15 +159,24 @@ def split(records, seed=0, train_frac=0.8):
     return [records[i] for i in order[:k]], [records[i] for i in order[k:]]
 
 
-def _arrays(records):
+# Instance weight in the training loss: (best time / mean best time)^alpha,
+# normalized to mean 1 (alpha 0: every instance alike). The regret that matters
+# is summed over instances, where long joins dominate.
+TRAIN_WEIGHT_ALPHA = 0.0
+
+
+def _arrays(records, alpha=0.0):
     X = np.array([r["features"] for r in records], dtype=np.float32)
     T = np.zeros((len(records), eg.SEL_CLASSES), dtype=np.float32)
     M = np.zeros_like(T)
+    best = np.array([min(t for t in r["times_ms"] if t is not None) for r in records], dtype=np.float64)
+    w = (best / best.mean()) ** alpha if alpha else np.ones_like(best)
+    w = w / w.mean()
     for i, r in enumerate(records):
         for c, t in enumerate(r["times_ms"]):
             if t is not None:
                 T[i, c] = math.log2(max(t, 1e-3))
-                M[i, c] = 1.0
+                M[i, c] = w[i]
     return X, T, M
 
 
@@ -171,9 +190,11 @@ def init_params(seed=0):
     return torch.cat(parts).float()
 
 
-def train(records, steps=3000, lr=3e-3, seed=0, device="cuda:0"):
-    """Full-batch Adam with the library's GPU kernels; returns a model dict."""
-    X, T, M = _arrays(records)
+def train(records, steps=3000, lr=3e-3, seed=0, device="cuda:0", alpha=None):
+    """Full-batch Adam with the library's GPU kernels (loss weights: the mask
+    carries each instance's weight, see TRAIN_WEIGHT_ALPHA); returns a model dict."""
+    alpha = TRAIN_WEIGHT_ALPHA if alpha is None else alpha
+    X, T, M = _arrays(records, alpha)
     mean = X.mean(axis=0)
     std = np.maximum(X.std(axis=0), 1e-3)
     Xn = (X - mean) / std
@@ -187,7 +208,7 @@ def train(records, steps=3000, lr=3e-3, seed=0, device="cuda:0"):
             losses.append(float(tr.loss.item()))
     return {"params": tr.params.cpu(), "mean": mean.astype(np.float32), "std": std.astype(np.float32),
             "lo": X.min(axis=0), "hi": X.max(axis=0),
-            "losses": losses, "steps": steps, "lr": lr, "seed": seed}
+            "losses": losses, "steps": steps, "lr": lr, "seed": seed, "alpha": alpha}
 
 
 def predict_classes(model, records, device="cuda:0"):
@@ -231,7 +252,8 @@ def save_model(model, path=MODEL_PATH, extra=None):
            "hidden": eg.MLP_HIDDEN, "params": [float(v) for v in model["params"].tolist()],
            "mean": [float(v) for v in model["mean"]], "std": [float(v) for v in model["std"]],
            "domain": {"lo": [float(v) for v in model["lo"]], "hi": [float(v) for v in model["hi"]]},
-           "train": {"steps": model["steps"], "lr": model["lr"], "seed": model["seed"], "losses": model["losses"]}}
+           "train": {"steps": model["steps"], "lr": model["lr"], "seed": model["seed"], "losses": model["losses"],
+                     "weight_alpha": model.get("alpha", 0.0)}}
     if extra:
         doc.update(extra)
     with open(path, "w") as f:
@@ -261,7 +283,30 @@ FAMILIES = {
     2: dict(n_instances=771, seed=8, family=2, min_build_log2=16.0, max_build_log2=26.0, max_probe_log2=28.0),
     3: dict(n_instances=243, seed=9, family=3, min_build_log2=22.0, max_build_log2=28.0, max_probe_log2=29.0),
 }
-FAMILY_PATHS = {1: DATA_PATH, 2: DATA_PATH_WIDE, 3: DATA_PATH_LARGE}
+FAMILY_PATHS = {1: DATA_PATH, 2: DATA_PATH_WIDE, 3: DATA_PATH_LARGE, 4: DATA_PATH_SHAPED}
+
+
+def collect_shaped(path, reps=3, device="cuda:0", log=print):
+    """Family 4: time every class on the SHAPED instances (resumable by index)."""
+    import synth
+    done = set()
+    if os.path.exists(path):
+        with open(path) as f:
+            done = {json.loads(line)["idx"] for line in f}
+    with open(path, "a") as f:
+        for idx, (gen, kw) in enumerate(SHAPED):
+            if idx in done:
+                continue
+            inp = getattr(synth, gen)(device=device, **kw)
+            rec = measure_instance(inp, reps)
+            rec.update({"idx": idx, "seed": kw["seed"], "params": {"family": 4, "generator": gen, **kw},
+                        "n_build": inp.n_build, "n_probe": inp.n_probe})
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            ts = [t for t in rec["times_ms"] if t is not None]
+            log(f"shaped {idx} {gen} {kw}: best {min(ts):.3f} ms" if ts else f"shaped {idx}: skipped")
+            del inp
+            torch.cuda.empty_cache()
 
 
 def main(argv=None):
@@ -273,24 +318,28 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="paper_2607_04489_amd.selector")
     sub = ap.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
-    c.add_argument("--family", type=int, choices=sorted(FAMILIES), required=True)
+    c.add_argument("--family", type=int, choices=sorted(FAMILIES) + [4], required=True)
     c.add_argument("--out", default=None)
     c.add_argument("--time-limit", type=float, default=None)
     t = sub.add_parser("train")
     t.add_argument("--out", default=MODEL_PATH)
     t.add_argument("--steps", type=int, default=2000)
+    t.add_argument("--alpha", type=float, default=None, help="instance weight exponent (default TRAIN_WEIGHT_ALPHA)")
     args = ap.parse_args(argv)
     if args.cmd == "collect":
+        if args.family == 4:
+            collect_shaped(args.out or DATA_PATH_SHAPED)
+            return
         kw = dict(FAMILIES[args.family])
         n = kw.pop("n_instances")
         collect(args.out or FAMILY_PATHS[args.family], n, time_limit_s=args.time_limit, log_every=10, **kw)
         return
     recs = load_records()
     train_set, test_set = split(recs, seed=0)
-    model = train(train_set, steps=args.steps, lr=3e-3, seed=0)
+    model = train(train_set, steps=args.steps, lr=3e-3, seed=0, alpha=args.alpha)
     ev = evaluate(model, test_set)
     by_family = {}
-    for f in sorted(FAMILIES):
+    for f in sorted(FAMILIES) + [4]:
         part = [r for r in test_set if r.get("params", {}).get("family", 1) == f]
         if part:
             by_family[f"family{f}"] = evaluate(model, part)
