@@ -89,14 +89,23 @@ __global__ void k_hash_build(const K *__restrict__ keys, const PB *__restrict__ 
   }
 }
 
-// Table clear for the key-claiming build: key = sentinel, row id = empty.
+// Table clear for the key-claiming build: key = sentinel, row id = empty. Slots
+// are 16 or 32 bytes (one or two 16-byte words); each workgroup stores one
+// contiguous chunk of the table with 16-byte stores, as the library's fills do.
 template <typename K, typename PB>
 __global__ void __launch_bounds__(256) k_hash_clear(Slot<K, PB> *__restrict__ slots, uint64_t n, K sentinel) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  constexpr int kWords = sizeof(Slot<K, PB>) / 16;
+  static_assert(kWords == 1 || kWords == 2, "16- or 32-byte slots");
   Slot<K, PB> e{};
   e.key = sentinel;
   e.rowid = kEmpty;
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) slots[i] = e;
+  uint4 w[kWords];
+  __builtin_memcpy(w, &e, sizeof(e));
+  uint4 *__restrict__ q = reinterpret_cast<uint4 *>(slots);
+  const uint64_t nw = n * kWords;
+  const uint64_t per = (nw + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = uint64_t(blockIdx.x) * per, hi = min(nw, lo + per);
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) q[i] = w[i % kWords];
 }
 
 // Build that claims a slot by CAS on its key word (empty = a sentinel value no
@@ -192,8 +201,9 @@ int hash_impl(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
   HashTab<K, PB> tab{slots, nslots - 1, dup, false};
   K sentinel;
   if (hash_sentinel<K>(a, &sentinel)) {
-    EIGER_LAUNCH("hash_clear", (k_hash_clear<K, PB>), dim3(grid_for(nslots, 256 * 4, 8)), dim3(256), 0, s, slots,
-                 nslots, sentinel);
+    EIGER_LAUNCH("hash_clear", (k_hash_clear<K, PB>),
+                 dim3(static_cast<unsigned>(std::min<uint64_t>((nslots + 1023) / 1024, uint64_t(device_cu_count()) * 16))),
+                 dim3(256), 0, s, slots, nslots, sentinel);
     EIGER_LAUNCH("hash_build", (k_hash_build_keys<K, PB>), dim3(grid_for(a.nR, 256 * 2, 8)), dim3(256), 0, s,
                  static_cast<const K *>(a.bk), static_cast<const PB *>(a.bp), a.nR, slots, nslots - 1, sentinel,
                  dup, &c->flags);
