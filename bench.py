@@ -185,8 +185,8 @@ def batch_bytes(nb, npr, lf=0.5, radix_bits=0):
     region (16-byte slots, sized as the library sizes them for load factor lf),
     or for a partitioned join its partitioned copies (key, payload, row id per
     row and pass) and counters."""
-    if radix_bits:
-        return 8 * nb + 8 * npr + 8 * npr + 2 * 12 * (nb + npr) + (1 << 22)
+    if radix_bits:  # partitioned joins share one workspace region (counted by the caller)
+        return 8 * nb + 8 * npr + 8 * npr + (1 << 22)
     slots = 64
     while slots < nb / lf + 1.0:
         slots <<= 1
@@ -213,7 +213,7 @@ def batch_waves(sizes, budget, tune=None):
     return waves
 
 
-def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=False, seed=42):
+def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=False, seed=42, save_tune=None):
     """4,096 independent unique-key int32 joins of uneven sizes (build rows
     2^U(8,22), probe rows 4-16x, match rate U[0.1,1], half dense / half sparse).
     The batch does not fit HBM at once (inputs, outputs and tables of all joins
@@ -230,7 +230,9 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
     max_np = max(n for _, n in sizes)
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    budget = int(free * 0.85) - 24 * max_np - (1 << 30)
+    # the largest join's partitioned copies (the shared partitioned-join workspace)
+    max_nb = max(n for n, _ in sizes)
+    budget = int(free * 0.85) - 24 * max_np - 2 * 12 * (max_nb + max_np) - (1 << 30)
     tune = None
     if not autotune and os.path.exists(batchmod.TUNE_PATH):
         tune = batchmod.load()
@@ -242,7 +244,12 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
         inputs = [synth.batched_join(seed, j, log2_lo, log2_hi, device=dev) for j in idx]
         joins = [(i.build_keys, i.build_payload, i.probe_keys, i.probe_payload) for i in inputs]
         if autotune and tune is None:
-            tune, _ = batchmod.autotune(joins, log=log)
+            tune, table = batchmod.autotune(joins, log=log)
+            if save_tune:
+                batchmod.save(tune, save_tune, table)
+            import gc
+            gc.collect()
+            torch.cuda.empty_cache()
         b = eg.Batch(joins, tune)
         b.launch()
         torch.cuda.synchronize()
@@ -590,8 +597,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-joins comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the rule-planner comparison of the learned plan")
     ap.add_argument("--autotune", action="store_true", help="autotune the batched graph before timing it")
+    ap.add_argument("--save-tune", default="", metavar="PATH", help="batched: write the autotuned knobs here")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-key sort and group-by points")
     ap.add_argument("--skf-config", default="", help="skf_sort: one configuration KEYSxDTYPE, e.g. 4xint32")
+    ap.add_argument("--gb-config", default="", help="groupby: one cell DTYPExLOG2GROUPS, e.g. int32x20")
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.workload, args.kernel,
@@ -599,10 +608,15 @@ def main():
         return
     if args.workload == "batched":
         import torch  # noqa: F401
-        print(json.dumps(bench_batched(autotune=args.autotune)), flush=True)
+        print(json.dumps(bench_batched(autotune=args.autotune, save_tune=args.save_tune or None)), flush=True)
         return
     if args.workload == "groupby":
-        print(json.dumps(bench_groupby(reps=max(1, args.steps))), flush=True)
+        kw = {}
+        if args.gb_config:
+            import torch
+            d, lg = args.gb_config.split("x")
+            kw = {"groups_log2": (int(lg),), "dtypes": (getattr(torch, d),)}
+        print(json.dumps(bench_groupby(reps=max(1, args.steps), **kw)), flush=True)
         return
     if args.workload == "join_sweep":
         print(json.dumps(bench_join_sweep(reps=max(1, args.steps))), flush=True)

@@ -44,20 +44,22 @@ def time_graph(joins, tune, reps=3):
     return best
 
 
-def autotune(joins, candidates=None, reps=3, log=print):
-    """joins: list of (bk, bp, pk, pp). Returns {bucket: (lf, tile, bits)} and the timings."""
+def autotune(joins, candidates=None, reps=3, log=print, max_joins=64):
+    """joins: list of (bk, bp, pk, pp). Returns {bucket: (lf, tile, bits)} and the
+    timings; each bucket is timed on at most `max_joins` of its joins."""
     by_bucket = {}
     for q in joins:
         by_bucket.setdefault(eg.batch_bucket(q[0].numel()), []).append(q)
     tune, table = {}, {}
     for b in sorted(by_bucket):
         times = {}
+        sub = by_bucket[b][:max_joins]  # the same joins for every candidate
         for c in (candidates or candidates_for(b)):
-            times[tuple(c)] = time_graph(by_bucket[b], {b: tuple(c)}, reps)
+            times[tuple(c)] = time_graph(sub, {b: tuple(c)}, reps)
         best = min(times, key=times.get)
         tune[b] = best
         table[b] = {f"{lf}/{tile}/{bits}": round(t, 4) for (lf, tile, bits), t in times.items()}
-        log(f"bucket 2^{b}: {len(by_bucket[b])} joins, best lf={best[0]} tile={best[1]} radix_bits={best[2]} "
+        log(f"bucket 2^{b}: {len(sub)} of {len(by_bucket[b])} joins, best lf={best[0]} tile={best[1]} radix_bits={best[2]} "
             f"({times[best]:.3f} ms vs default {times.get((0.5, 16384, 0), float('nan')):.3f} ms)")
     return tune, table
 

@@ -329,9 +329,11 @@ int plan_batch(const eiger_batch_join *joins, int32_t n, int32_t kdt, int32_t pd
       Workspace dry(nullptr, 0);
       JoinCounters *unused = nullptr;
       if (int rc = run_join_variant(a, dry, &unused)) return rc;
-      job.ws_off = bp->radix_ws;
+      // the partitioned joins run one after another on the graph's stream, so
+      // they share one workspace region sized for the largest
+      job.ws_off = 0;
       job.ws_bytes = dry.used + 256;
-      bp->radix_ws += (job.ws_bytes + 255) & ~size_t(255);
+      bp->radix_ws = std::max(bp->radix_ws, (job.ws_bytes + 255) & ~size_t(255));
       bp->radix.push_back(job);
       bp->out_total += uint64_t(q.n_probe);
       continue;
