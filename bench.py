@@ -104,7 +104,8 @@ def summarize_profile(d, workload, kernel, plan=None):
         n = r["Name"]
         if "eiger" not in n:
             continue
-        short = n.split("::")[-1].split("(")[0] if "::" in n else n
+        head = n.replace("(anonymous namespace)::", "").split("(")[0]  # drop the argument list
+        short = head.replace("void ", "").replace("eiger::", "")
         table.append((float(r["TotalDurationNs"]), short[:60], int(r["Calls"]), float(r["AverageNs"])))
     table.sort(reverse=True)
     rec = {"workload": workload, "kernel": kernel, "plan": plan, "sources_sha": sources_digest(kernel),

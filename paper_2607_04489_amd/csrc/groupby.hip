@@ -22,12 +22,10 @@
 #include <cmath>
 #include <string>
 
+#include "sort.hpp"
 #include "variants.hpp"
 
 namespace eiger {
-
-int radix_partition_carry(int32_t kdt, const void *keys, uint64_t n, const WordCols &cols, int bits, int passes,
-                          Workspace &ws, PartitionedSide *out, hipStream_t s, bool run);
 
 namespace {
 
@@ -433,8 +431,8 @@ int gb_impl(const eiger_column &keys, const eiger_column *vals, int32_t nv, cons
   unsigned long long sentinel;
   gb_sentinel(plan, &sentinel);
   *lay = gb_layout(ws, static_cast<uint64_t>(plan.slots), nv, sentinel);
-  PartitionedSide part{};
-  WordCols wc{};
+  PartitionOut part{};
+  PartLanes wc{};
   if (plan.variant == EIGER_GB_PARTITION) {
     for (int32_t c = 0; c < nv; ++c) {
       const uint32_t *base = static_cast<const uint32_t *>(vals[c].data);
@@ -448,7 +446,7 @@ int gb_impl(const eiger_column &keys, const eiger_column *vals, int32_t nv, cons
         wc.stride[wc.n++] = 1;
       }
     }
-    int rc = radix_partition_carry(keys.dtype, keys.data, n, wc, plan.radix_bits, plan.radix_bits > 9 ? 2 : 1, ws,
+    int rc = radix_partition_lanes(static_cast<int>(dtype_size(keys.dtype)), keys.data, n, wc, plan.radix_bits, ws,
                                    &part, n > 0 ? s : nullptr, n > 0);
     if (rc) return rc;
   }

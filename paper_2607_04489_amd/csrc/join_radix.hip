@@ -1121,40 +1121,6 @@ int run_radix(const JoinArgs &a, Workspace &ws, JoinCounters **ctr) {
 #undef EIGER_DISPATCH
 }
 
-namespace {
-template <typename K>
-int partition_carry_impl(const K *keys, uint64_t n, const WordCols &cols, int bits, int passes, Workspace &ws,
-                         PartitionedSide *out, hipStream_t s, bool run) {
-  const PassPlan pp = split_bits(bits, passes);
-  const uint32_t F = 1u << (pp.bits[0] + pp.bits[1]);
-  WideSide<K> S = wide_side_layout<K>(ws, n, cols.n, pp);
-  const uint64_t nC = counters_len(n, pp);
-  uint32_t *C = ws.take<uint32_t>(nC);
-  uint64_t *tmp = ws.take<uint64_t>(scan_tmp_elems(std::max<uint64_t>(nC, F + 1)));
-  uint64_t *total = ws.take<uint64_t>(1);
-  const int last = pp.passes - 1;
-  out->keys = S.k[last];
-  out->rows = S.r[last];
-  for (int w = 0; w < kMaxWords; ++w) out->words[w] = w < cols.n ? S.w[last][w] : nullptr;
-  out->off = S.off;
-  if (!ws.base || !run) return EIGER_OK;
-  Lanes l{};
-  l.n = cols.n;
-  for (int w = 0; w < cols.n; ++w) {
-    l.src[w] = cols.src[w];
-    l.src_stride[w] = cols.stride[w];
-  }
-  return partition_side_carry<K>(keys, l, n, S, pp, C, tmp, total, s);
-}
-}  // namespace
-
-int radix_partition_carry(int32_t kdt, const void *keys, uint64_t n, const WordCols &cols, int bits, int passes,
-                          Workspace &ws, PartitionedSide *out, hipStream_t s, bool run) {
-  if (kdt == EIGER_INT64)
-    return partition_carry_impl<int64_t>(static_cast<const int64_t *>(keys), n, cols, bits, passes, ws, out, s, run);
-  return partition_carry_impl<int32_t>(static_cast<const int32_t *>(keys), n, cols, bits, passes, ws, out, s, run);
-}
-
 int run_radix_wide(const JoinArgs &a, const WordCols &colsR, const WordCols &colsS, Workspace &ws, JoinCounters **ctr,
                    WideSource *outR, WideSource *outS) {
   if (a.kdt == EIGER_INT64) return radix_wide_impl<int64_t>(a, colsR, colsS, ws, ctr, outR, outS);

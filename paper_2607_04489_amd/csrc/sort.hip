@@ -35,57 +35,80 @@ constexpr int items_per_thread() {
 }
 // Workgroups per CU of the grids; workgroups loop over the remaining tiles. The
 // histogram keeps one tile per workgroup; the scatter, whose workgroups hold
-// 70 KB of LDS, runs best with a few resident workgroups per CU.
+// up to 70 KB of LDS, runs best with a few resident workgroups per CU.
 constexpr uint64_t kHistPerCu = 64;
 constexpr uint64_t kScatPerCu = 8;
 
+// Digit of a plain sort: bits [shift, shift + width) of the key.
 template <typename K>
-constexpr int tile_items() {
-  return kSNT * items_per_thread<K>();
-}
+struct KeyDigit {
+  static constexpr bool kStore = false;  // cheap: recomputed from the key
+  int shift;
+  uint32_t mask;
+  __device__ __forceinline__ uint32_t operator()(K k) const { return static_cast<uint32_t>(k >> shift) & mask; }
+};
 
+// Digit of a key's partition id, the top `bits` bits of fmix64 of the
+// sign-extended key (hash partitioning).
 template <typename K>
-__device__ __forceinline__ uint32_t digit_of(K k, int shift, uint32_t mask) {
-  return static_cast<uint32_t>(k >> shift) & mask;
-}
+struct PartDigit {
+  static constexpr bool kStore = true;  // a hash per item: kept in LDS for the write-out
+  int top;                              // 64 - partition bits
+  int shift;
+  uint32_t mask;
+  __device__ __forceinline__ uint32_t operator()(K k) const {
+    return static_cast<uint32_t>((fmix64(static_cast<uint64_t>(sext(k))) >> top) >> shift) & mask;
+  }
+};
 
 // Workgroups loop over tiles (the grid is sized to the chip): one workgroup
 // per tile was limited by how fast workgroups are dispatched, not by memory.
-template <typename K>
-__global__ void __launch_bounds__(kSNT) k_sort_hist(const K *__restrict__ keys, uint64_t n, int shift,
-                                                    uint32_t mask, uint32_t ntiles, uint32_t *__restrict__ cnt) {
-  constexpr int kItems = items_per_thread<K>();
+template <typename K, int kItems, typename D>
+__global__ void __launch_bounds__(kSNT) k_sort_hist(const K *__restrict__ keys, uint64_t n, D dig, uint32_t ntiles,
+                                                    uint32_t *__restrict__ cnt) {
+  constexpr int T = kSNT * kItems;
   __shared__ uint32_t h[kSDigits];
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t base = static_cast<uint64_t>(tile) * tile_items<K>();
+    const uint64_t base = static_cast<uint64_t>(tile) * T;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint64_t i = base + static_cast<uint64_t>(j) * kSNT + threadIdx.x;
-      if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+      if (i < n) atomicAdd(&h[dig(keys[i])], 1u);
     }
     __syncthreads();
-    if (threadIdx.x <= mask) cnt[static_cast<uint64_t>(threadIdx.x) * ntiles + tile] = h[threadIdx.x];
+    if (threadIdx.x <= dig.mask) cnt[static_cast<uint64_t>(threadIdx.x) * ntiles + tile] = h[threadIdx.x];
     __syncthreads();
   }
 }
 
-// vin == nullptr: the values are the row ids (first pass of a permutation sort).
-template <typename K>
-__global__ void __launch_bounds__(kSNT) k_sort_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-                                                       uint64_t n, int shift, int bits, uint32_t ntiles,
-                                                       const uint32_t *__restrict__ offs, K *__restrict__ kout,
-                                                       uint32_t *__restrict__ vout) {
-  constexpr int kItems = items_per_thread<K>();
-  constexpr int T = tile_items<K>();
+// 32-bit value lanes moved along with the keys. Lane w of row i is
+// src[w][i * stride[w]]; a NULL source lane means the row id i itself.
+constexpr int kSortLanes = 4;
+struct LanesIn {
+  const uint32_t *src[kSortLanes];
+  uint32_t stride[kSortLanes];
+};
+struct LanesOut {
+  uint32_t *dst[kSortLanes];
+};
+
+// One LSD pass: rank each tile's items stably by digit, place them digit-major
+// in LDS, write each digit's run of the tile to its global position.
+template <typename K, int NW, int kItems, typename D>
+__global__ void __launch_bounds__(kSNT) k_sort_scatter(const K *__restrict__ kin, LanesIn vin, uint64_t n, D dig,
+                                                       int bits, uint32_t ntiles, const uint32_t *__restrict__ offs,
+                                                       K *__restrict__ kout, LanesOut vout) {
+  constexpr int T = kSNT * kItems;
+  constexpr int NL = NW > 0 ? NW : 1;
   __shared__ K sk[T];
-  __shared__ uint32_t sv[T];
+  __shared__ uint32_t sv[NL][NW > 0 ? T : 1];
+  __shared__ uint8_t sd[D::kStore ? T : 1];
   __shared__ uint32_t wcnt[kSWaves][kSDigits];
   __shared__ uint32_t dstart[kSDigits];
   __shared__ uint32_t adj[kSDigits];
   __shared__ uint32_t scan_tmp[kSWaves + 1];
-  const uint32_t mask = (1u << bits) - 1u;
   const int lane = __lane_id();
   const int w = threadIdx.x / 64;
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -95,19 +118,22 @@ __global__ void __launch_bounds__(kSNT) k_sort_scatter(const K *__restrict__ kin
     const uint64_t base = static_cast<uint64_t>(tile) * T;
     const uint64_t wbase = base + static_cast<uint64_t>(w) * (64 * kItems);
     K key[kItems];
-    uint32_t val[kItems], lo[kItems];
+    uint32_t val[NL][kItems], lo[kItems], dg[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
       const bool ok = i < n;
       key[j] = ok ? kin[i] : K(0);
-      val[j] = ok ? (vin ? vin[i] : static_cast<uint32_t>(i)) : 0u;
+#pragma unroll
+      for (int v = 0; v < NW; ++v)
+        val[v][j] = ok ? (vin.src[v] ? vin.src[v][i * vin.stride[v]] : static_cast<uint32_t>(i)) : 0u;
     }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
       const bool ok = i < n;
-      const uint32_t d = digit_of(key[j], shift, mask);
+      const uint32_t d = dig(key[j]);
+      dg[j] = d;
       uint64_t peers = __ballot(ok);
 #pragma unroll
       for (int b = 0; b < kSDigitBits; ++b) {
@@ -139,25 +165,33 @@ __global__ void __launch_bounds__(kSNT) k_sort_scatter(const K *__restrict__ kin
     const uint32_t ds = block_exclusive_scan<kSNT, uint32_t>(tot, scan_tmp, &all);
     dstart[t] = ds;
     // global start of this tile's run of digit t, minus its start inside the tile
-    adj[t] = static_cast<uint32_t>(t) <= mask ? offs[static_cast<uint64_t>(t) * ntiles + tile] - ds : 0u;
+    adj[t] = static_cast<uint32_t>(t) <= dig.mask ? offs[static_cast<uint64_t>(t) * ntiles + tile] - ds : 0u;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const uint64_t i = wbase + static_cast<uint64_t>(j) * 64 + lane;
       if (i < n) {
-        const uint32_t d = digit_of(key[j], shift, mask);
+        const uint32_t d = D::kStore ? dg[j] : dig(key[j]);
         const uint32_t p = dstart[d] + wcnt[w][d] + lo[j];
         sk[p] = key[j];
-        sv[p] = val[j];
+#pragma unroll
+        for (int v = 0; v < NW; ++v) sv[v][p] = val[v][j];
+        if constexpr (D::kStore) sd[p] = static_cast<uint8_t>(d);
       }
     }
     __syncthreads();
     const uint32_t in_tile = static_cast<uint32_t>(min<uint64_t>(T, n - base));
     for (uint32_t p = threadIdx.x; p < in_tile; p += kSNT) {
       const K k = sk[p];
-      const uint32_t o = adj[digit_of(k, shift, mask)] + p;
+      uint32_t d;
+      if constexpr (D::kStore)
+        d = sd[p];
+      else
+        d = dig(k);
+      const uint32_t o = adj[d] + p;
       kout[o] = k;
-      vout[o] = sv[p];
+#pragma unroll
+      for (int v = 0; v < NW; ++v) vout.dst[v][o] = sv[v][p];
     }
     __syncthreads();
   }
@@ -173,17 +207,72 @@ __global__ void __launch_bounds__(256) k_sort_copy(const K *__restrict__ kin, co
   }
 }
 
+// Count-table and temporaries of the passes over n items in tiles of T.
+template <typename K, int NW>
+struct PassBufs {
+  uint64_t ntiles;
+  uint32_t *cnt;
+  uint64_t *tmp, *total;
+  K *k2;
+  uint32_t *v2[NW > 0 ? NW : 1];
+};
+
+template <typename K, int NW>
+PassBufs<K, NW> pass_bufs(Workspace &ws, uint64_t n, int T) {
+  PassBufs<K, NW> b{};
+  b.ntiles = (n + T - 1) / T;
+  const uint64_t ncnt = b.ntiles * kSDigits;
+  b.cnt = ws.take<uint32_t>(ncnt);
+  b.tmp = ws.take<uint64_t>(scan_tmp_elems(ncnt));
+  b.total = ws.take<uint64_t>(1);
+  b.k2 = ws.take<K>(n);
+  for (int v = 0; v < NW; ++v) b.v2[v] = ws.take<uint32_t>(n);
+  return b;
+}
+
+// ceil(total_bits / digit_bits) stable passes of balanced digit widths, least
+// significant digit first, alternating between (kout, vout) and the
+// temporaries so that the last pass lands in (kout, vout). make(shift, mask)
+// gives the pass's digit functor.
+template <typename K, int NW, int kItems, typename MakeDigit>
+int lsd_passes(const K *kin, LanesIn vin, uint64_t n, int total_bits, int digit_bits, K *kout, LanesOut vout,
+               const PassBufs<K, NW> &b, MakeDigit make, hipStream_t s) {
+  const int passes = (total_bits + digit_bits - 1) / digit_bits;
+  const unsigned hist_grid =
+      static_cast<unsigned>(std::min<uint64_t>(b.ntiles, uint64_t(device_cu_count()) * kHistPerCu));
+  const unsigned scat_grid =
+      static_cast<unsigned>(std::min<uint64_t>(b.ntiles, uint64_t(device_cu_count()) * kScatPerCu));
+  int shift = 0;
+  const K *src_k = kin;
+  LanesIn src_v = vin;
+  for (int p = 0; p < passes; ++p) {
+    const int bits = (total_bits - shift + (passes - p) - 1) / (passes - p);
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    K *dk = to_out ? kout : b.k2;
+    LanesOut dv{};
+    for (int v = 0; v < NW; ++v) dv.dst[v] = to_out ? vout.dst[v] : b.v2[v];
+    const auto dig = make(shift, (1u << bits) - 1u);
+    EIGER_LAUNCH("sort_hist", (k_sort_hist<K, kItems, decltype(dig)>), dim3(hist_grid), dim3(kSNT), 0, s, src_k, n,
+                 dig, static_cast<uint32_t>(b.ntiles), b.cnt);
+    int rc = exclusive_scan_u32(b.cnt, b.cnt, (static_cast<uint64_t>(dig.mask) + 1) * b.ntiles, b.tmp, b.total, s);
+    if (rc) return rc;
+    EIGER_LAUNCH("sort_scatter", (k_sort_scatter<K, NW, kItems, decltype(dig)>), dim3(scat_grid), dim3(kSNT), 0, s,
+                 src_k, src_v, n, dig, bits, static_cast<uint32_t>(b.ntiles), b.cnt, dk, dv);
+    src_k = dk;
+    for (int v = 0; v < NW; ++v) {
+      src_v.src[v] = dv.dst[v];
+      src_v.stride[v] = 1;
+    }
+    shift += bits;
+  }
+  return EIGER_OK;
+}
+
 template <typename K>
 int sort_impl(const K *kin, const uint32_t *vin, uint64_t n, int key_bits, K *kout, uint32_t *vout, Workspace &ws,
               hipStream_t s) {
-  constexpr int T = tile_items<K>();
-  const uint64_t ntiles = (n + T - 1) / T;
-  const uint64_t ncnt = ntiles * kSDigits;
-  uint32_t *cnt = ws.take<uint32_t>(ncnt);
-  uint64_t *tmp = ws.take<uint64_t>(scan_tmp_elems(ncnt));
-  uint64_t *total = ws.take<uint64_t>(1);
-  K *k2 = ws.take<K>(n);
-  uint32_t *v2 = ws.take<uint32_t>(n);
+  constexpr int kItems = items_per_thread<K>();
+  const PassBufs<K, 1> b = pass_bufs<K, 1>(ws, n, kSNT * kItems);
   if (!ws.base || n == 0) return EIGER_OK;
   const int passes = (key_bits + kSDigitBits - 1) / kSDigitBits;
   if (passes == 0 || n == 1) {
@@ -191,32 +280,105 @@ int sort_impl(const K *kin, const uint32_t *vin, uint64_t n, int key_bits, K *ko
     EIGER_LAUNCH("sort_copy", k_sort_copy<K>, dim3(grid), dim3(256), 0, s, kin, vin, n, kout, vout);
     return EIGER_OK;
   }
-  // balanced digit widths, least significant digit first; the last pass lands in out
-  const unsigned hist_grid = static_cast<unsigned>(std::min<uint64_t>(ntiles, uint64_t(device_cu_count()) * kHistPerCu));
-  const unsigned scat_grid = static_cast<unsigned>(std::min<uint64_t>(ntiles, uint64_t(device_cu_count()) * kScatPerCu));
-  int shift = 0;
-  const K *src_k = kin;
-  const uint32_t *src_v = vin;
-  for (int p = 0; p < passes; ++p) {
-    const int bits = (key_bits - shift + (passes - p) - 1) / (passes - p);
-    const bool to_out = ((passes - 1 - p) % 2) == 0;
-    K *dk = to_out ? kout : k2;
-    uint32_t *dv = to_out ? vout : v2;
-    const uint32_t mask = (1u << bits) - 1u;
-    EIGER_LAUNCH("sort_hist", k_sort_hist<K>, dim3(hist_grid), dim3(kSNT), 0, s, src_k, n,
-                 shift, mask, static_cast<uint32_t>(ntiles), cnt);
-    int rc = exclusive_scan_u32(cnt, cnt, (static_cast<uint64_t>(mask) + 1) * ntiles, tmp, total, s);
-    if (rc) return rc;
-    EIGER_LAUNCH("sort_scatter", k_sort_scatter<K>, dim3(scat_grid), dim3(kSNT), 0, s, src_k,
-                 src_v, n, shift, bits, static_cast<uint32_t>(ntiles), cnt, dk, dv);
-    src_k = dk;
-    src_v = dv;
-    shift += bits;
+  LanesIn in{};
+  in.src[0] = vin;
+  in.stride[0] = 1;
+  LanesOut out{};
+  out.dst[0] = vout;
+  return lsd_passes<K, 1, kItems>(kin, in, n, key_bits, kSDigitBits, kout, out, b,
+                                  [](int shift, uint32_t mask) { return KeyDigit<K>{shift, mask}; }, s);
+}
+
+// Partition bounds: off[p] = first position whose partition id is >= p (the
+// rows are sorted by partition id), off[F] = n.
+template <typename K>
+__global__ void __launch_bounds__(256) k_part_bounds(const K *__restrict__ keys, uint64_t n, int bits, uint32_t F,
+                                                     uint32_t *__restrict__ off) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p <= F; p += stride) {
+    uint64_t a = 0, b = n;
+    while (a < b) {
+      const uint64_t m = a + (b - a) / 2;
+      if ((fmix64(static_cast<uint64_t>(sext(keys[m]))) >> (64 - bits)) < p)
+        a = m + 1;
+      else
+        b = m;
+    }
+    off[p] = static_cast<uint32_t>(a);
   }
+}
+
+// Tile items for hash partitioning: the largest count (at most 32 per thread)
+// whose LDS copy (key, lanes, digit byte) stays within 64 KB, two workgroups per CU.
+template <typename K, int NW>
+constexpr int part_items() {
+  constexpr int per = 65536 / (kSNT * static_cast<int>(sizeof(K) + 4 * NW + 1));
+  return per > 32 ? 32 : per;
+}
+
+// Widest digit of a partitioning pass: at least 32 items of a tile per digit on
+// average, so each digit's run of the tile is written in whole lines more often
+// (2^28 rows, 4-byte keys and two 4-byte lanes, 4,864-item tiles: 14 bits in
+// two 7-bit passes 7.6 ms, 16 bits in two 8-bit passes 11.2 ms).
+constexpr int part_digit_bits(int tile) {
+  int b = 1;
+  while (b < kSDigitBits && (tile >> (b + 1)) >= 32) ++b;
+  return b;
+}
+
+template <typename K, int NW>
+int partition_impl(const K *keys, uint64_t n, const PartLanes &cols, int bits, Workspace &ws, PartitionOut *out,
+                   hipStream_t s, bool run) {
+  constexpr int kItems = part_items<K, NW>();
+  const uint32_t F = 1u << bits;
+  K *ok = ws.take<K>(n ? n : 1);
+  LanesOut ov{};
+  for (int v = 0; v < NW; ++v) ov.dst[v] = ws.take<uint32_t>(n ? n : 1);
+  uint32_t *off = ws.take<uint32_t>(uint64_t(F) + 1);
+  const PassBufs<K, NW> b = pass_bufs<K, NW>(ws, n, kSNT * kItems);
+  out->keys = ok;
+  for (int v = 0; v < kSortLanes; ++v) out->words[v] = v < NW ? ov.dst[v] : nullptr;
+  out->off = off;
+  if (!ws.base || !run) return EIGER_OK;
+  if (n > 0) {
+    LanesIn in{};
+    for (int v = 0; v < NW; ++v) {
+      in.src[v] = cols.src[v];
+      in.stride[v] = cols.stride[v];
+    }
+    const int top = 64 - bits;
+    int rc = lsd_passes<K, NW, kItems>(
+        keys, in, n, bits, part_digit_bits(kSNT * kItems), ok, ov, b,
+        [top](int shift, uint32_t mask) { return PartDigit<K>{top, shift, mask}; }, s);
+    if (rc) return rc;
+  }
+  EIGER_LAUNCH("part_bounds", k_part_bounds<K>, dim3(static_cast<unsigned>(std::min<uint64_t>((F + 256) / 256, 1024))),
+               dim3(256), 0, s, ok, n, bits, F, off);
   return EIGER_OK;
 }
 
+template <typename K>
+int partition_lanes(const K *keys, uint64_t n, const PartLanes &cols, int bits, Workspace &ws, PartitionOut *out,
+                    hipStream_t s, bool run) {
+  switch (cols.n) {
+    case 0: return partition_impl<K, 0>(keys, n, cols, bits, ws, out, s, run);
+    case 1: return partition_impl<K, 1>(keys, n, cols, bits, ws, out, s, run);
+    case 2: return partition_impl<K, 2>(keys, n, cols, bits, ws, out, s, run);
+    case 3: return partition_impl<K, 3>(keys, n, cols, bits, ws, out, s, run);
+    default: return partition_impl<K, 4>(keys, n, cols, bits, ws, out, s, run);
+  }
+}
+
 }  // namespace
+
+int radix_partition_lanes(int key_bytes, const void *keys, uint64_t n, const PartLanes &cols, int bits, Workspace &ws,
+                          PartitionOut *out, hipStream_t s, bool run) {
+  if (bits < 1 || bits > 24 || cols.n < 0 || cols.n > kSortLanes)
+    return fail(EIGER_ERR_INVALID_ARG, "radix partition: bits in [1, 24], at most 4 lanes");
+  if (key_bytes == 8)
+    return partition_lanes<int64_t>(static_cast<const int64_t *>(keys), n, cols, bits, ws, out, s, run);
+  return partition_lanes<int32_t>(static_cast<const int32_t *>(keys), n, cols, bits, ws, out, s, run);
+}
 
 int radix_sort_pairs(int key_bytes, const void *kin, const uint32_t *vin, uint64_t n, int key_bits, void *kout,
                      uint32_t *vout, Workspace &ws, hipStream_t s) {

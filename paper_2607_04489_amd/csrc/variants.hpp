@@ -53,19 +53,6 @@ struct WideSource {
 // in the final partitioned arrays, described by *outR / *outS.
 int run_radix_wide(const JoinArgs &a, const WordCols &colsR, const WordCols &colsS, Workspace &ws, JoinCounters **ctr,
                    WideSource *outR, WideSource *outS);
-// One side partitioned on the top bits of its key hash, carrying word lanes:
-// keys (of the key dtype), row ids, one word array per lane, and partition
-// offsets (2^bits + 1).
-struct PartitionedSide {
-  const void *keys;
-  const uint32_t *rows;
-  const uint32_t *words[kMaxWords];
-  const uint32_t *off;
-};
-// Lays out (always) and, with a workspace base and `run`, enqueues the
-// partitioning of one side in `passes` passes of 2^bits partitions in all.
-int radix_partition_carry(int32_t kdt, const void *keys, uint64_t n, const WordCols &cols, int bits, int passes,
-                          Workspace &ws, PartitionedSide *out, hipStream_t s, bool run);
 // Dispatch of eiger_join's variants (abi.hip).
 int run_join_variant(const JoinArgs &a, Workspace &ws, JoinCounters **ctr);
 
