@@ -214,14 +214,16 @@ def batch_waves(sizes, budget, tune=None):
     return waves
 
 
-def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=False, seed=42, save_tune=None):
+def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=False, seed=42, save_tune=None,
+                  compare=True):
     """4,096 independent unique-key int32 joins of uneven sizes (build rows
     2^U(8,22), probe rows 4-16x, match rate U[0.1,1], half dense / half sparse).
     The batch does not fit HBM at once (inputs, outputs and tables of all joins
     are ~380 GB), so the joins are drawn and run in the fewest consecutive
     waves that fit: per wave one captured hipGraph (per-join plan on the
     device), timed, then one eiger_join call sequence per join (rule plan, and
-    fixed GLOBAL_HASH) for comparison. Returns a summary dict."""
+    fixed GLOBAL_HASH) for comparison (skipped with compare=False, e.g. to
+    trace the graph's kernels alone). Returns a summary dict."""
     import torch
     import paper_2607_04489_amd as eg
     import synth
@@ -281,11 +283,13 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
             torch.cuda.synchronize()
             return (time.perf_counter() - t0) * 1e3, [(r.count, r.checksum) for r in res]
 
-        t_rule, rres = per_join(eg.SEL_RULE)
-        t_fixed, _ = per_join(eg.SEL_FIXED_HASH)
+        t_rule = t_fixed = 0.0
+        if compare:
+            t_rule, rres = per_join(eg.SEL_RULE)
+            t_fixed, _ = per_join(eg.SEL_FIXED_HASH)
+            agree = agree and all(r == (int(c), int(s_)) for r, c, s_ in zip(rres, counts, sums))
         rule_ms += t_rule
         fixed_ms += t_fixed
-        agree = agree and all(r == (int(c), int(s_)) for r, c, s_ in zip(rres, counts, sums))
         pairs += int(counts.sum())
         direct += int((variants == eg.DIRECT).sum())
         radix += int((variants == eg.RADIX).sum())
@@ -300,10 +304,10 @@ def bench_batched(n_joins=4096, log2_lo=8.0, log2_hi=22.0, reps=3, autotune=Fals
             "graph_ms": round(graph_ms, 3), "graph_probe_tuples_per_s": n_probe / (graph_ms * 1e-3),
             "graph_alg_GBps": round((8 * n_build + 8 * n_probe + 8 * pairs) / (graph_ms * 1e-3) / 1e9, 1),
             "per_join_rule_ms": round(rule_ms, 3), "per_join_fixed_hash_ms": round(fixed_ms, 3),
-            "speedup_vs_per_join_rule": round(rule_ms / graph_ms, 2),
-            "speedup_vs_per_join_fixed_hash": round(fixed_ms / graph_ms, 2),
+            "speedup_vs_per_join_rule": round(rule_ms / graph_ms, 2) if compare else None,
+            "speedup_vs_per_join_fixed_hash": round(fixed_ms / graph_ms, 2) if compare else None,
             "direct_joins": direct, "radix_joins": radix, "flagged": flagged,
-            "agrees_with_single_joins": bool(agree), "tuned": tune is not None,
+            "agrees_with_single_joins": bool(agree) if compare else None, "tuned": tune is not None,
             "workload": (f"{n_joins} unique-key int32 joins, build rows 2^U({log2_lo:g},{log2_hi:g}), probe 4-16x "
                          f"build, match U[0.1,1], half dense / half sparse keys; drawn and run in "
                          f"{len(waves)} waves that fit HBM")}
@@ -609,7 +613,8 @@ def main():
         return
     if args.workload == "batched":
         import torch  # noqa: F401
-        print(json.dumps(bench_batched(autotune=args.autotune, save_tune=args.save_tune or None)), flush=True)
+        print(json.dumps(bench_batched(autotune=args.autotune, save_tune=args.save_tune or None,
+                                       compare=not args.no_compare)), flush=True)
         return
     if args.workload == "groupby":
         kw = {}
