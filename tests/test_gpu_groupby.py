@@ -90,3 +90,21 @@ def test_groupby_edges(gpu):
     with pytest.raises(eg.EigerError) as err:
         eg.groupby(both, [], forced(both, eg.GB_HASH))
     assert err.value.code == eg.EIGER_ERR_UNSUPPORTED
+
+
+# PARTITION over every lane count (0-4 value words: none, int32, two int32,
+# int64 + int32, two int64) and one to three partitioning passes (digits of at
+# most 8 bits, narrower for wide rows: 7 bits for 12-byte rows, 6 for 24-byte).
+LANES = [("none", torch.int32, []), ("i32", torch.int32, [torch.int32]),
+         ("2xi32", torch.int32, [torch.int32, torch.int32]), ("i64+i32", torch.int64, [torch.int64, torch.int32]),
+         ("2xi64", torch.int64, [torch.int64, torch.int64])]
+
+
+@pytest.mark.parametrize("lanes", LANES, ids=[x[0] for x in LANES])
+@pytest.mark.parametrize("bits", [3, 9, 15, 18])
+def test_groupby_partition_lanes_and_passes(gpu, lanes, bits):
+    _, key_dtype, val_dtypes = lanes
+    keys, vals = synth.groupby_input(seed=bits, n=1_500_007, groups=400_000, key_dtype=key_dtype, n_vals=2,
+                                     val_dtype=torch.int64, device=gpu)
+    vals = [v.to(d) for v, d in zip(vals, val_dtypes)]
+    check(keys, vals, eg.groupby(keys, vals, forced(keys, eg.GB_PARTITION, bits)))
