@@ -243,6 +243,65 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     flush(L, o, static_cast<uint32_t>(fill));
     fill = 0;
   }
+  if constexpr (Tab::kRuns) {
+    static_assert(SCAP >= 2 * NT && NT <= 65536, "the stage holds a round's row table");
+    if (total > SCAP) {
+      // More matches than the stage holds (duplicated build keys; the stage is
+      // empty here). Reserve the sub-tile's output range, then expand one row
+      // slot k at a time (NT rows per round): the round's row table goes into
+      // the stage arrays, and the pairs are written by consecutive threads at
+      // consecutive positions, each reading its build row by index from the
+      // key's run.
+      const uint64_t base = reserve(L, o, total);
+      uint64_t done = 0;  // pairs of this sub-tile placed so far (uniform)
+      // row table: rd[i] = run start of row i minus the index of its first
+      // pair (mod 2^32), so pair g of row i is build row tab.row_at(rd[i] + g);
+      // rq[i] = its probe row id; row_of: the row of each pair of a chunk
+      uint32_t *rd = L.b, *rq = L.b + NT;
+      uint16_t *row_of = reinterpret_cast<uint16_t *>(L.p);
+      constexpr uint32_t CH = 2 * SCAP;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        uint64_t tk;
+        const uint64_t ok = block_exclusive_scan<NT, uint64_t>(cnt[k], L.scan, &tk);
+        if (tk == 0) continue;
+        if (tk >= (uint64_t(1) << 32)) {  // offsets do not fit the row table: per row
+          uint64_t pos = base + done + ok;
+          const uint32_t rr = r.rid[k];
+          emit_matches(tab, r.key[k], cnt[k], first[k], [&](uint32_t b) { put_pair(o, pos++, b, rr); });
+          done += tk;
+          continue;
+        }
+        rd[threadIdx.x] = first[k] - static_cast<uint32_t>(ok);
+        rq[threadIdx.x] = r.rid[k];
+        // pairs of the round in chunks of CH: each thread marks its row on its
+        // pairs' entries of `row_of`, then consecutive threads take consecutive
+        // pairs, so the stores are coalesced
+        for (uint64_t c0 = 0; c0 < tk; c0 += CH) {
+          const uint64_t c1 = c0 + CH < tk ? c0 + CH : tk;
+          const uint64_t a = ok > c0 ? ok : c0;
+          const uint64_t e = ok + cnt[k] < c1 ? ok + cnt[k] : c1;
+          for (uint64_t g = a; g < e; ++g) row_of[g - c0] = static_cast<uint16_t>(threadIdx.x);
+          __syncthreads();
+          uint64_t g = c0 + threadIdx.x;
+          for (; g + NT < c1; g += 2 * NT) {  // two pairs per step: two lookup chains in flight
+            const uint32_t i0 = row_of[g - c0], i1 = row_of[g + NT - c0];
+            const uint32_t b0 = tab.row_at(rd[i0] + static_cast<uint32_t>(g));
+            const uint32_t b1 = tab.row_at(rd[i1] + static_cast<uint32_t>(g + NT));
+            put_pair(o, base + done + g, b0, rq[i0]);
+            put_pair(o, base + done + g + NT, b1, rq[i1]);
+          }
+          if (g < c1) {
+            const uint32_t i = row_of[g - c0];
+            put_pair(o, base + done + g, tab.row_at(rd[i] + static_cast<uint32_t>(g)), rq[i]);
+          }
+          __syncthreads();
+        }
+        done += tk;
+      }
+      return;
+    }
+  }
   if (total > SCAP) {
     // More matches than the stage holds (duplicated build keys; the stage is
     // empty here): reserve the sub-tile's whole output range with one atomic,
