@@ -260,10 +260,26 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
       uint32_t *rd = L.b, *rq = L.b + NT;
       uint16_t *row_of = reinterpret_cast<uint16_t *>(L.p);
       constexpr uint32_t CH = 2 * SCAP;
+      // every round's offsets from one scan of 16-bit fields when the whole
+      // sub-tile has fewer than 2^16 pairs (no field can carry into the next)
+      constexpr bool kPack = IPT <= 4;
+      const bool packed = kPack && total < (uint64_t(1) << 16);
+      uint64_t pk_ok = 0, pk_tot = 0;
+      if (packed) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) v |= static_cast<uint64_t>(cnt[k]) << (16 * k);
+        pk_ok = block_exclusive_scan<NT, uint64_t>(v, L.scan, &pk_tot);
+      }
 #pragma unroll
       for (int k = 0; k < IPT; ++k) {
-        uint64_t tk;
-        const uint64_t ok = block_exclusive_scan<NT, uint64_t>(cnt[k], L.scan, &tk);
+        uint64_t tk, ok;
+        if (packed) {
+          ok = (pk_ok >> (16 * k)) & 0xFFFFu;
+          tk = (pk_tot >> (16 * k)) & 0xFFFFu;
+        } else {
+          ok = block_exclusive_scan<NT, uint64_t>(cnt[k], L.scan, &tk);
+        }
         if (tk == 0) continue;
         if (tk >= (uint64_t(1) << 32)) {  // offsets do not fit the row table: per row
           uint64_t pos = base + done + ok;
