@@ -243,7 +243,9 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
     flush(L, o, static_cast<uint32_t>(fill));
     fill = 0;
   }
-  if constexpr (Tab::kRuns) {
+  // (probes of 8 rows per thread keep the per-row path below: the row table's
+  // registers would cost them occupancy)
+  if constexpr (Tab::kRuns && IPT <= 4) {
     static_assert(SCAP >= 2 * NT && NT <= 65536, "the stage holds a round's row table");
     if (total > SCAP) {
       // More matches than the stage holds (duplicated build keys; the stage is
@@ -262,8 +264,7 @@ __device__ __forceinline__ void probe_process(const Tab &tab, const ProbeRegs<IP
       constexpr uint32_t CH = 2 * SCAP;
       // every round's offsets from one scan of 16-bit fields when the whole
       // sub-tile has fewer than 2^16 pairs (no field can carry into the next)
-      constexpr bool kPack = IPT <= 4;
-      const bool packed = kPack && total < (uint64_t(1) << 16);
+      const bool packed = total < (uint64_t(1) << 16);
       uint64_t pk_ok = 0, pk_tot = 0;
       if (packed) {
         uint64_t v = 0;
