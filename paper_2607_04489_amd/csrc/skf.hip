@@ -52,6 +52,26 @@ struct Rows {
 // result is used, so each thread keeps several memory accesses in flight.
 constexpr int kDeBatch = 8;
 
+// Step 1 for one value: its slot in the global table (claimed if new). The
+// value kDeEmpty (INT64_MIN) has the extra slot mask + 1; a full walk gives
+// mask + 2 and raises the overflow flag.
+__device__ __forceinline__ uint64_t de_slot(const DeTable &t, unsigned long long k) {
+  if (k == kDeEmpty) {
+    t.ctr[1] = 1u;
+    return t.mask + 1;
+  }
+  uint64_t h = fmix64(k) & t.mask;
+  const uint64_t limit = t.mask < kDeMaxProbe ? t.mask + 1 : kDeMaxProbe;
+  for (uint64_t probe = 0; probe < limit; ++probe) {
+    unsigned long long cur = t.key[h];
+    if (cur == kDeEmpty) cur = atomicCAS(&t.key[h], kDeEmpty, k);
+    if (cur == kDeEmpty || cur == k) return h;
+    h = (h + 1) & t.mask;
+  }
+  t.ctr[2] = 1u;
+  return t.mask + 2;
+}
+
 // One row per thread and step: a batched form (all rows' first table reads in
 // flight before any is resolved) measured slower on a hot, L2-resident table.
 template <typename K>
@@ -59,26 +79,121 @@ __global__ void __launch_bounds__(kDeNT) k_de_insert(Rows<K> rows, DeTable t, ui
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kDeNT;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kDeNT + threadIdx.x; i < rows.n; i += stride) {
     const unsigned long long k = static_cast<unsigned long long>(static_cast<int64_t>(*rows.at(i)));
-    uint64_t slot;
-    if (k == kDeEmpty) {
-      slot = t.mask + 1;
-      t.ctr[1] = 1u;
+    loc[i] = static_cast<uint32_t>(de_slot(t, k));
+  }
+}
+
+// Step 1 for tables of few distinct values: each workgroup keeps the distinct
+// values it has met, with their global slots, in an LDS table for all of its
+// chunks of kDeNT * kDeLdsRows rows. A chunk first enters its rows' values into
+// the LDS table, then the values new to the workgroup are claimed in the
+// global table (one walk per value and workgroup, not per row), then every row
+// takes its value's slot from LDS. A value that finds no LDS slot within
+// kDeLdsProbe steps takes the global walk itself, as does INT64_MIN. The
+// global table has at most kDeLdsMaxTable slots, so at most half as many
+// distinct values: the LDS table stays at most half full.
+constexpr uint32_t kDeLdsSlots = 4096;
+constexpr int kDeLdsRows = 16;
+constexpr uint32_t kDeLdsProbe = 64;
+constexpr uint32_t kDeLdsNone = 0xFFFFFFFFu;
+constexpr uint64_t kDeLdsMaxTable = 4096;  // global tables up to this many slots use it
+constexpr int kDeLdsPerCu = 3;             // 48 KB of LDS per workgroup
+
+// kVec: 4-byte keys from one 16-byte aligned array (and a 16-byte aligned loc):
+// each thread loads and stores four consecutive rows at once.
+template <typename K, bool kVec>
+__global__ void __launch_bounds__(kDeNT) k_de_insert_lds(Rows<K> rows, DeTable t, uint32_t *__restrict__ loc) {
+  __shared__ unsigned long long lk[kDeLdsSlots];
+  __shared__ uint32_t lg[kDeLdsSlots];
+  constexpr uint64_t C = static_cast<uint64_t>(kDeNT) * kDeLdsRows;
+  const uint64_t nch = (rows.n + C - 1) / C;
+  for (uint32_t j = threadIdx.x; j < kDeLdsSlots; j += kDeNT) {
+    lk[j] = kDeEmpty;
+    lg[j] = kDeLdsNone;
+  }
+  __syncthreads();
+  for (uint64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    // row r of this thread: kVec groups of four consecutive rows, else rows
+    // kDeNT apart
+    auto row = [&](int r) -> uint64_t {
+      if constexpr (kVec)
+        return ch * C + (static_cast<uint64_t>(r / 4) * kDeNT + threadIdx.x) * 4 + (r % 4);
+      else
+        return ch * C + threadIdx.x + static_cast<uint64_t>(r) * kDeNT;
+    };
+    unsigned long long key[kDeLdsRows];
+    uint32_t li[kDeLdsRows];
+    if constexpr (kVec) {
+#pragma unroll
+      for (int q = 0; q < kDeLdsRows; q += 4) {
+        const uint64_t i = row(q);
+        if (i + 3 < rows.n) {
+          const int4 v = *reinterpret_cast<const int4 *>(rows.a + i);
+          key[q] = static_cast<unsigned long long>(static_cast<int64_t>(v.x));
+          key[q + 1] = static_cast<unsigned long long>(static_cast<int64_t>(v.y));
+          key[q + 2] = static_cast<unsigned long long>(static_cast<int64_t>(v.z));
+          key[q + 3] = static_cast<unsigned long long>(static_cast<int64_t>(v.w));
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            key[q + u] = i + u < rows.n ? static_cast<unsigned long long>(static_cast<int64_t>(rows.a[i + u])) : kDeEmpty;
+        }
+      }
     } else {
-      uint64_t h = fmix64(k) & t.mask;
-      slot = t.mask + 2;  // no slot: only reached with the overflow flag set
-      const uint64_t limit = t.mask < kDeMaxProbe ? t.mask + 1 : kDeMaxProbe;
-      for (uint64_t probe = 0; probe < limit; ++probe) {
-        unsigned long long cur = t.key[h];
-        if (cur == kDeEmpty) cur = atomicCAS(&t.key[h], kDeEmpty, k);
-        if (cur == kDeEmpty || cur == k) {
-          slot = h;
+#pragma unroll
+      for (int r = 0; r < kDeLdsRows; ++r) {
+        const uint64_t i = row(r);
+        key[r] = i < rows.n ? static_cast<unsigned long long>(static_cast<int64_t>(*rows.at(i))) : kDeEmpty;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kDeLdsRows; ++r) {
+      li[r] = kDeLdsNone;
+      if (key[r] == kDeEmpty) continue;
+      uint32_t h = static_cast<uint32_t>(fmix64(key[r])) & (kDeLdsSlots - 1);
+      for (uint32_t probe = 0; probe < kDeLdsProbe; ++probe) {
+        unsigned long long cur = lk[h];
+        if (cur == kDeEmpty) cur = atomicCAS(&lk[h], kDeEmpty, key[r]);
+        if (cur == kDeEmpty || cur == key[r]) {
+          li[r] = h;
           break;
         }
-        h = (h + 1) & t.mask;
+        h = (h + 1) & (kDeLdsSlots - 1);
       }
-      if (slot == t.mask + 2) t.ctr[2] = 1u;
     }
-    loc[i] = static_cast<uint32_t>(slot);
+    __syncthreads();
+    // values new to this workgroup: claim them in the global table
+    for (uint32_t j = threadIdx.x; j < kDeLdsSlots; j += kDeNT) {
+      if (lg[j] != kDeLdsNone) continue;
+      const unsigned long long k = lk[j];
+      if (k != kDeEmpty) lg[j] = static_cast<uint32_t>(de_slot(t, k));
+    }
+    __syncthreads();
+    // (the next chunk only claims empty LDS slots and fills their lg entries,
+    // which no row of this chunk reads, so no barrier follows)
+    uint32_t out[kDeLdsRows];
+#pragma unroll
+    for (int r = 0; r < kDeLdsRows; ++r)
+      out[r] = li[r] != kDeLdsNone ? lg[li[r]] : (row(r) < rows.n ? static_cast<uint32_t>(de_slot(t, key[r])) : 0u);
+    if constexpr (kVec) {
+#pragma unroll
+      for (int q = 0; q < kDeLdsRows; q += 4) {
+        const uint64_t i = row(q);
+        if (i + 3 < rows.n) {
+          *reinterpret_cast<uint4 *>(loc + i) = make_uint4(out[q], out[q + 1], out[q + 2], out[q + 3]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (i + u < rows.n) loc[i + u] = out[q + u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kDeLdsRows; ++r) {
+        const uint64_t i = row(r);
+        if (i < rows.n) loc[i] = out[r];
+      }
+    }
   }
 }
 
@@ -338,7 +453,19 @@ size_t skf_layout(Workspace &ws, const eiger_skf_plan_t &p, uint64_t n, bool sor
 template <typename K>
 int de_launch_insert(const DictBufs &d, const void *a, const void *b, uint64_t na, uint64_t n, hipStream_t s) {
   Rows<K> r{static_cast<const K *>(a), static_cast<const K *>(b), na, n};
-  EIGER_LAUNCH("dict_insert", k_de_insert<K>, dim3(grid_for(n)), dim3(kDeNT), 0, s, r, d.t, d.loc);
+  if (d.t.mask + 1 <= kDeLdsMaxTable) {
+    const uint64_t chunks = (n + uint64_t(kDeNT) * kDeLdsRows - 1) / (uint64_t(kDeNT) * kDeLdsRows);
+    const unsigned grid =
+        static_cast<unsigned>(std::max<uint64_t>(1, std::min<uint64_t>(chunks, uint64_t(device_cu_count()) * kDeLdsPerCu)));
+    bool vec = false;
+    if constexpr (sizeof(K) == 4) {
+      vec = na == n && reinterpret_cast<uintptr_t>(a) % 16 == 0 && reinterpret_cast<uintptr_t>(d.loc) % 16 == 0;
+      if (vec) EIGER_LAUNCH("dict_insert", (k_de_insert_lds<K, true>), dim3(grid), dim3(kDeNT), 0, s, r, d.t, d.loc);
+    }
+    if (!vec) EIGER_LAUNCH("dict_insert", (k_de_insert_lds<K, false>), dim3(grid), dim3(kDeNT), 0, s, r, d.t, d.loc);
+  } else {
+    EIGER_LAUNCH("dict_insert", k_de_insert<K>, dim3(grid_for(n)), dim3(kDeNT), 0, s, r, d.t, d.loc);
+  }
   return EIGER_OK;
 }
 
