@@ -257,6 +257,7 @@ struct FuseKey {
   uint64_t flip;                 // all-ones over the width for a descending key, else 0
   int32_t wide;                  // 8-byte key column
   int32_t dict;
+  uint32_t slots1;               // DICT: entries of code_of_slot (table slots + 1)
   int32_t bits;
   int32_t shift;
 };
@@ -414,6 +415,121 @@ struct SkfLayout {
   void *sorted;   // sort: sorted keys when the caller passes none
 };
 
+// Fusion over 16-byte accesses: each thread takes groups of four consecutive
+// rows, reads each key column (or dictionary slot ids) four rows at a time and
+// writes four fused keys at once. Used when every column is one array with
+// 16-byte aligned rows. With kLdsCodes the dictionaries' code tables (at most
+// kFuseLdsCodes entries in all) are first copied into LDS, so the per-row code
+// lookups are LDS reads.
+constexpr uint32_t kFuseLdsCodes = 9216;  // 36 KB
+constexpr int kFuseGroups = 2;            // groups of four rows per thread and step
+
+template <typename F, bool kLdsCodes>
+__global__ void __launch_bounds__(kDeNT) k_skf_fuse_vec(FuseArgs A, uint32_t lds_off0, uint32_t lds_total) {
+  __shared__ uint32_t codes[kLdsCodes ? kFuseLdsCodes : 1];
+  uint32_t lds_off[EIGER_SKF_MAX_KEYS];
+  if constexpr (kLdsCodes) {
+    uint32_t o = lds_off0;
+    for (int c = 0; c < A.nk; ++c) {
+      lds_off[c] = o;
+      if (A.k[c].dict && A.k[c].bits) {
+        const uint32_t m = A.k[c].slots1;
+        for (uint32_t j = threadIdx.x; j < m; j += kDeNT) codes[o + j] = A.k[c].code_of_slot[j];
+        o += m;
+      }
+    }
+    (void)lds_total;
+    __syncthreads();
+  }
+  constexpr uint64_t span = uint64_t(kDeNT) * 4 * kFuseGroups;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * span;
+  for (uint64_t base = static_cast<uint64_t>(blockIdx.x) * span; base < A.n; base += stride) {
+    uint64_t i0[kFuseGroups];
+    bool full[kFuseGroups];
+#pragma unroll
+    for (int g = 0; g < kFuseGroups; ++g) {
+      i0[g] = base + (static_cast<uint64_t>(g) * kDeNT + threadIdx.x) * 4;
+      full[g] = i0[g] + 3 < A.n;
+    }
+    F f[kFuseGroups][4];
+#pragma unroll
+    for (int g = 0; g < kFuseGroups; ++g)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[g][u] = 0;
+    for (int c = 0; c < A.nk; ++c) {
+      const FuseKey &k = A.k[c];
+      if (k.bits == 0) continue;
+      uint64_t code[kFuseGroups][4];
+#pragma unroll
+      for (int g = 0; g < kFuseGroups; ++g) {
+        const uint64_t i = i0[g];
+        if (k.dict) {
+          uint32_t sl[4] = {0u, 0u, 0u, 0u};
+          if (full[g]) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(k.loc + i);
+            sl[0] = v.x; sl[1] = v.y; sl[2] = v.z; sl[3] = v.w;
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sl[u] = i + u < A.n ? k.loc[i + u] : 0u;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if constexpr (kLdsCodes)
+              code[g][u] = codes[lds_off[c] + sl[u]];
+            else
+              code[g][u] = i + u < A.n ? k.code_of_slot[sl[u]] : 0u;
+          }
+        } else if (k.wide) {
+          const int64_t *a = static_cast<const int64_t *>(k.a);
+          int64_t v[4] = {0, 0, 0, 0};
+          if (full[g]) {
+            const longlong2 x = *reinterpret_cast<const longlong2 *>(a + i);
+            const longlong2 y = *reinterpret_cast<const longlong2 *>(a + i + 2);
+            v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = i + u < A.n ? a[i + u] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) code[g][u] = static_cast<uint64_t>(v[u]) - k.base;
+        } else {
+          const int32_t *a = static_cast<const int32_t *>(k.a);
+          int32_t v[4] = {0, 0, 0, 0};
+          if (full[g]) {
+            const int4 x = *reinterpret_cast<const int4 *>(a + i);
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = i + u < A.n ? a[i + u] : 0;
+          }
+          // exact: every key is at least the minimum
+#pragma unroll
+          for (int u = 0; u < 4; ++u) code[g][u] = static_cast<uint64_t>(static_cast<int64_t>(v[u])) - k.base;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f[g][u] |= static_cast<F>((code[g][u] ^ k.flip) << k.shift);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < kFuseGroups; ++g) {
+      F *out = static_cast<F *>(A.out_a);
+      const uint64_t i = i0[g];
+      if (full[g]) {
+        if constexpr (sizeof(F) == 4) {
+          *reinterpret_cast<uint4 *>(out + i) = make_uint4(f[g][0], f[g][1], f[g][2], f[g][3]);
+        } else {
+          *reinterpret_cast<ulonglong2 *>(out + i) = make_ulonglong2(f[g][0], f[g][1]);
+          *reinterpret_cast<ulonglong2 *>(out + i + 2) = make_ulonglong2(f[g][2], f[g][3]);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i + u < A.n) out[i + u] = f[g][u];
+      }
+    }
+  }
+}
+
 // Sizes the sort workspace for the largest distinct-value sort and the row sort.
 size_t sort_ws_bytes(int key_bytes, uint64_t n, int bits) {
   Workspace w(nullptr, 0);
@@ -534,10 +650,36 @@ int launch_fuse(const eiger_skf_plan_t &p, const eiger_column *ka, const eiger_c
     f.dict = k.code == EIGER_SKF_DICT;
     f.loc = L.d[c].loc;
     f.code_of_slot = L.d[c].code_of_slot;
+    f.slots1 = f.dict ? static_cast<uint32_t>(k.slots + 1) : 0u;
     f.base = static_cast<uint64_t>(k.base);
     f.bits = k.bits;
     f.shift = k.shift;
     f.flip = k.descending && k.bits ? (k.bits == 64 ? ~0ull : ((1ull << k.bits) - 1)) : 0ull;
+  }
+  // 16-byte form: every column one 16-byte aligned array, output too
+  bool vec = na == n && reinterpret_cast<uintptr_t>(out_a) % 16 == 0;
+  uint64_t lds_codes = 0;
+  for (int c = 0; c < p.n_keys; ++c) {
+    vec = vec && reinterpret_cast<uintptr_t>(ka[c].data) % 16 == 0;
+    if (p.key[c].code == EIGER_SKF_DICT && p.key[c].bits) lds_codes += A.k[c].slots1;
+  }
+  if (vec) {
+    const uint64_t units = (n + 4 * kFuseGroups - 1) / (4 * kFuseGroups);
+    const unsigned g = grid_for(units);
+    const bool lds = lds_codes <= kFuseLdsCodes;
+    const uint32_t lt = static_cast<uint32_t>(lds_codes);
+    if (p.fused_bytes == 4) {
+      if (lds)
+        EIGER_LAUNCH("skf_fuse", (k_skf_fuse_vec<uint32_t, true>), dim3(g), dim3(kDeNT), 0, s, A, 0u, lt);
+      else
+        EIGER_LAUNCH("skf_fuse", (k_skf_fuse_vec<uint32_t, false>), dim3(g), dim3(kDeNT), 0, s, A, 0u, lt);
+    } else {
+      if (lds)
+        EIGER_LAUNCH("skf_fuse", (k_skf_fuse_vec<uint64_t, true>), dim3(g), dim3(kDeNT), 0, s, A, 0u, lt);
+      else
+        EIGER_LAUNCH("skf_fuse", (k_skf_fuse_vec<uint64_t, false>), dim3(g), dim3(kDeNT), 0, s, A, 0u, lt);
+    }
+    return EIGER_OK;
   }
   const unsigned grid = grid_for((n + kDeBatch - 1) / kDeBatch);
   if (p.fused_bytes == 4) {

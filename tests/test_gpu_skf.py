@@ -163,3 +163,14 @@ def test_join_multikey(gpu, n_keys, dtype):
     want = skf.join_multikey([host(r) for r in R], [host(s) for s in S])
     got = oracle.canonical_pairs(host(res.build_rowid).astype(np.uint32), host(res.probe_rowid).astype(np.uint32))
     assert res.count == want.size and np.array_equal(got, want)
+
+
+def test_fuse_vector_and_scalar_forms(gpu):
+    # aligned columns take the 16-byte fusion form, a view one row in takes the
+    # per-row form; both must give the oracle's fused keys (ragged tails too)
+    cols = synth.multikey_table(17, 300_007, device=gpu, **TABLES["4xi32_8b"])
+    for view in (cols, [c[1:] for c in cols], [c[:299_999] for c in cols]):
+        want_plan, hc, codes = oracle_plan(view, [False, True, False, False])
+        fa, _, fin = eg.skf_fuse(view, plan=eg.skf_plan([eg.stats(c) for c in view], [False, True, False, False]))
+        same_plan(fin, want_plan)
+        assert np.array_equal(host(fa).view(np.uint32), skf.fuse(hc, want_plan, codes))
