@@ -63,19 +63,42 @@ struct PartDigit {
 
 // Workgroups loop over tiles (the grid is sized to the chip): one workgroup
 // per tile was limited by how fast workgroups are dispatched, not by memory.
-template <typename K, int kItems, typename D>
+// kVec (16-byte aligned keys): each thread reads 16 bytes of consecutive keys
+// per load (counting does not depend on which thread holds which key).
+template <typename K, int kItems, typename D, bool kVec>
 __global__ void __launch_bounds__(kSNT) k_sort_hist(const K *__restrict__ keys, uint64_t n, D dig, uint32_t ntiles,
                                                     uint32_t *__restrict__ cnt) {
   constexpr int T = kSNT * kItems;
+  constexpr int V = 16 / static_cast<int>(sizeof(K));  // keys per 16-byte load
+  constexpr int NV = T / V;                            // 16-byte loads per tile (T is a multiple of 256)
   __shared__ uint32_t h[kSDigits];
   for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t base = static_cast<uint64_t>(tile) * T;
+    if constexpr (kVec) {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const uint64_t i = base + static_cast<uint64_t>(j) * kSNT + threadIdx.x;
-      if (i < n) atomicAdd(&h[dig(keys[i])], 1u);
+      for (int j = 0; j < (NV + kSNT - 1) / kSNT; ++j) {
+        const int q = j * kSNT + static_cast<int>(threadIdx.x);
+        if (q >= NV) break;
+        const uint64_t i = base + static_cast<uint64_t>(q) * V;
+        if (i + V <= n) {
+          K v[V];
+          *reinterpret_cast<uint4 *>(v) = *reinterpret_cast<const uint4 *>(keys + i);
+#pragma unroll
+          for (int u = 0; u < V; ++u) atomicAdd(&h[dig(v[u])], 1u);
+        } else {
+#pragma unroll
+          for (int u = 0; u < V; ++u)
+            if (i + u < n) atomicAdd(&h[dig(keys[i + u])], 1u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const uint64_t i = base + static_cast<uint64_t>(j) * kSNT + threadIdx.x;
+        if (i < n) atomicAdd(&h[dig(keys[i])], 1u);
+      }
     }
     __syncthreads();
     if (threadIdx.x <= dig.mask) cnt[static_cast<uint64_t>(threadIdx.x) * ntiles + tile] = h[threadIdx.x];
@@ -252,8 +275,12 @@ int lsd_passes(const K *kin, LanesIn vin, uint64_t n, int total_bits, int digit_
     LanesOut dv{};
     for (int v = 0; v < NW; ++v) dv.dst[v] = to_out ? vout.dst[v] : b.v2[v];
     const auto dig = make(shift, (1u << bits) - 1u);
-    EIGER_LAUNCH("sort_hist", (k_sort_hist<K, kItems, decltype(dig)>), dim3(hist_grid), dim3(kSNT), 0, s, src_k, n,
-                 dig, static_cast<uint32_t>(b.ntiles), b.cnt);
+    if (reinterpret_cast<uintptr_t>(src_k) % 16 == 0)
+      EIGER_LAUNCH("sort_hist", (k_sort_hist<K, kItems, decltype(dig), true>), dim3(hist_grid), dim3(kSNT), 0, s,
+                   src_k, n, dig, static_cast<uint32_t>(b.ntiles), b.cnt);
+    else
+      EIGER_LAUNCH("sort_hist", (k_sort_hist<K, kItems, decltype(dig), false>), dim3(hist_grid), dim3(kSNT), 0, s,
+                   src_k, n, dig, static_cast<uint32_t>(b.ntiles), b.cnt);
     int rc = exclusive_scan_u32(b.cnt, b.cnt, (static_cast<uint64_t>(dig.mask) + 1) * b.ntiles, b.tmp, b.total, s);
     if (rc) return rc;
     EIGER_LAUNCH("sort_scatter", (k_sort_scatter<K, NW, kItems, decltype(dig)>), dim3(scat_grid), dim3(kSNT), 0, s,
