@@ -17,8 +17,8 @@ constexpr int kHllM = 1 << kHllP;
 
 // ---------------------------------------------------------------- device math
 
-// MurmurHash3 64-bit finalizer (Appleby): the one key hash of the library, used
-// by the sketch registers, by hash-table slots and by radix partition ids.
+// MurmurHash3 64-bit finalizer (Appleby): the key hash of the sketch registers,
+// of hash-table slots and of radix partition ids of 8-byte keys.
 __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   k ^= k >> 33;
   k *= 0xff51afd7ed558ccdull;
@@ -31,6 +31,24 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
 template <typename T>
 __device__ __forceinline__ int64_t sext(T v) {
   return static_cast<int64_t>(v);
+}
+
+// Partition hash: radix partitions are the top bits of this value. 8-byte keys
+// take fmix64; 4-byte keys the 32-bit MurmurHash3 finalizer (Appleby) in the
+// upper half, a third of the instructions for the same top-bit mixing.
+template <typename K>
+__device__ __forceinline__ uint64_t part_hash(K key) {
+  if constexpr (sizeof(K) == 4) {
+    uint32_t h = static_cast<uint32_t>(key);
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return static_cast<uint64_t>(h) << 32;
+  } else {
+    return fmix64(static_cast<uint64_t>(sext(key)));
+  }
 }
 
 // Lane-level exclusive prefix of a 64-lane mask: number of set bits below this lane.

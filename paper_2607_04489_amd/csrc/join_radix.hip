@@ -4,7 +4,7 @@
 // The paper's partitioned hash join (Section 3.2, Table 1; its internals are
 // those of Wu et al., which the paper cites rather than prints) is re-derived
 // here for gfx950:
-//  * Both sides are partitioned on the top bits of fmix64(key) (hashing before
+//  * Both sides are partitioned on the top bits of part_hash(key) (hashing before
 //    partitioning evens out partition sizes, as the paper does for its
 //    partitioned group-by, Section 3.3), in one or two passes of at most 9 bits.
 //  * A pass is histogram -> exclusive scan -> scatter. The scatter sorts a tile
@@ -41,8 +41,9 @@ constexpr int kJSCAP = 2048;    // staged output pairs
 constexpr int kTableBytes = 48 * 1024;
 constexpr uint32_t kJTile = 32768;  // probe rows per work item
 
-__device__ __forceinline__ uint32_t bucket_of(uint64_t key_bits, int shift, uint32_t mask) {
-  return static_cast<uint32_t>(fmix64(key_bits) >> shift) & mask;
+// Bucket of a partition hash (part_hash) in a pass of `mask + 1` buckets.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t h, int shift, uint32_t mask) {
+  return static_cast<uint32_t>(h >> shift) & mask;
 }
 
 // Largest s with cpre[s] <= c, over s in [0, nseg).
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(kPNT)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t i = i0 + u * kPNT + threadIdx.x;
-      if (i < hi) atomicAdd(&hist[bucket_of(static_cast<uint64_t>(sext(kk[u])), shift, B - 1)], 1u);
+      if (i < hi) atomicAdd(&hist[bucket_of(part_hash(kk[u]), shift, B - 1)], 1u);
     }
   }
   __syncthreads();
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(kPNT)
     for (int k = 0; k < kPIPT; ++k) {
       const uint32_t i = t0 + k * kPNT + threadIdx.x;
       if (i < t1) {
-        bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
+        bk[k] = bucket_of(part_hash(key[k]), shift, B - 1);
         rk[k] = atomicAdd(&hist[bk[k]], 1u);
       }
     }
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(kPNT)
     for (int k = 0; k < kPIPT; ++k) {
       const uint32_t i = t0 + k * kPNT + threadIdx.x;
       if (i < t1) {
-        bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
+        bk[k] = bucket_of(part_hash(key[k]), shift, B - 1);
         rk[k] = atomicAdd(&hist[bk[k]], 1u);
       }
     }
@@ -908,7 +909,7 @@ __global__ void __launch_bounds__(kPNT)
       if (i < t1) {
         key[k] = keys[i];
         row[k] = kRows ? rows[i] : i;
-        bk[k] = bucket_of(static_cast<uint64_t>(sext(key[k])), shift, B - 1);
+        bk[k] = bucket_of(part_hash(key[k]), shift, B - 1);
         rk[k] = atomicAdd(&hist[bk[k]], 1u);
       }
     }
@@ -1189,7 +1190,7 @@ __global__ void k_cache_unique(const K *__restrict__ keys, uint64_t n, int bits,
   for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
     if (*static_cast<volatile uint32_t *>(dup)) return;
     const K key = keys[r];
-    const uint32_t p = static_cast<uint32_t>(fmix64(static_cast<uint64_t>(sext(key))) >> (64 - bits));
+    const uint32_t p = static_cast<uint32_t>(part_hash(key) >> (64 - bits));
     CacheTab<K, PB> tab{table + table_off[p], table_off[p + 1] - table_off[p], false};
     uint32_t c = 0;
     tab.for_each(key, [&](uint32_t) { ++c; });
@@ -1222,8 +1223,8 @@ __global__ void k_cache_build(const K *__restrict__ keys, const PB *__restrict__
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t r = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n; r += stride) {
     const K key = keys[r];
-    const uint64_t h = fmix64(static_cast<uint64_t>(sext(key)));
-    const uint32_t p = static_cast<uint32_t>(h >> (64 - bits));
+    const uint64_t h = fmix64(static_cast<uint64_t>(sext(key)));  // slot within the region
+    const uint32_t p = static_cast<uint32_t>(part_hash(key) >> (64 - bits));
     const uint32_t base = table_off[p], ns = table_off[p + 1] - base;
     uint32_t i = fastrange32(h, ns);
     for (;;) {

@@ -48,8 +48,8 @@ struct KeyDigit {
   __device__ __forceinline__ uint32_t operator()(K k) const { return static_cast<uint32_t>(k >> shift) & mask; }
 };
 
-// Digit of a key's partition id, the top `bits` bits of fmix64 of the
-// sign-extended key (hash partitioning).
+// Digit of a key's partition id, the top `bits` bits of its partition hash
+// (hash partitioning).
 template <typename K>
 struct PartDigit {
   static constexpr bool kStore = true;  // a hash per item: kept in LDS for the write-out
@@ -57,7 +57,7 @@ struct PartDigit {
   int shift;
   uint32_t mask;
   __device__ __forceinline__ uint32_t operator()(K k) const {
-    return static_cast<uint32_t>((fmix64(static_cast<uint64_t>(sext(k))) >> top) >> shift) & mask;
+    return static_cast<uint32_t>((part_hash(k) >> top) >> shift) & mask;
   }
 };
 
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(256) k_part_bounds(const K *__restrict__ keys,
     uint64_t a = 0, b = n;
     while (a < b) {
       const uint64_t m = a + (b - a) / 2;
-      if ((fmix64(static_cast<uint64_t>(sext(keys[m]))) >> (64 - bits)) < p)
+      if ((part_hash(keys[m]) >> (64 - bits)) < p)
         a = m + 1;
       else
         b = m;

@@ -12,7 +12,7 @@ int radix_sort_pairs(int key_bytes, const void *kin, const uint32_t *vin, uint64
                      uint32_t *vout, Workspace &ws, hipStream_t s);
 
 // Hash partitioning with value lanes: rows are ordered by partition id, the top
-// `bits` bits of fmix64 of the sign-extended key, by stable passes of the same
+// `bits` bits of the key's partition hash (part_hash), by stable passes of the same
 // sort (digits of at most 8 bits, narrower for wide rows); up to 4 32-bit lanes move along (lane w of row i is
 // src[w][i * stride[w]]). out receives the partitioned keys, the lanes (stride 1)
 // and off[0..2^bits] (partition p is [off[p], off[p + 1])). Always lays out
