@@ -108,3 +108,17 @@ def test_groupby_partition_lanes_and_passes(gpu, lanes, bits):
                                      val_dtype=torch.int64, device=gpu)
     vals = [v.to(d) for v, d in zip(vals, val_dtypes)]
     check(keys, vals, eg.groupby(keys, vals, forced(keys, eg.GB_PARTITION, bits)))
+
+
+@pytest.mark.parametrize("key_dtype", [torch.int32, torch.int64])
+def test_groupby_row_group_and_per_row_loads(gpu, key_dtype):
+    # aligned columns are read four rows at a time, views one row in per row;
+    # partitions start anywhere, so the four-row groups also mask rows before
+    # a partition's start (odd lengths give ragged ends)
+    keys, vals = synth.groupby_input(seed=9, n=300_001, groups=5000, key_dtype=key_dtype, n_vals=2,
+                                     val_dtype=torch.int64, device=gpu)
+    vals = [vals[0], vals[1].to(torch.int32)]
+    for view in (0, 1):
+        k, v = keys[view:], [x[view:] for x in vals]
+        for variant, bits in ((eg.GB_HASH, 0), (eg.GB_PARTITION, 3), (eg.GB_PARTITION, 9)):
+            check(k, v, eg.groupby(k, v, forced(k, variant, bits)))
