@@ -261,7 +261,8 @@ typedef enum { EIGER_GB_HASH = 0, EIGER_GB_PARTITION = 1 } eiger_groupby_variant
 
 typedef struct {
     int32_t variant;          /* eiger_groupby_variant */
-    int32_t radix_bits;       /* PARTITION: 2^radix_bits partitions (1..18; one pass up to 9 bits) */
+    int32_t radix_bits;       /* PARTITION: 2^radix_bits partitions (1..18), made by stable radix
+                                 passes of at most 8 bits (narrower for wide rows) */
     int32_t key_dtype;
     uint32_t flags;           /* EIGER_GB_* */
     int64_t slots;            /* slots of the global group table (power of two >= 1024) */
