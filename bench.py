@@ -508,7 +508,7 @@ def bench_join_sweep(reps=3, seed=42):
 
 
 def host_cores():
-    """Host CPUs this process may run on (the GPU machine grants 16)."""
+    """Host CPUs this process may run on (its CPU affinity), at most 16."""
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
