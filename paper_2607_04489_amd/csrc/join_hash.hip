@@ -22,7 +22,7 @@ namespace eiger {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kIPT = 4;
+constexpr int kIPT = 5;
 constexpr int kSCAP = 4096;
 
 template <typename K, typename PB>
