@@ -46,6 +46,26 @@ SHAPED = ([("sparse_unique64", dict(seed=100 + i, n_build=1 << b, n_probe=1 << p
           [("skewed_dup32", dict(seed=120 + i, n_distinct=1 << d, n_probe=1 << p, zipf_s=z))
            for i, (d, p, z) in enumerate([(23, 28, 0.5), (24, 27, 1.0), (24, 28, 0.75), (24, 28, 1.25),
                                           (23, 27, 1.5), (22, 28, 1.0), (24, 28, 0.3), (23, 28, 1.1)])])
+
+
+def _shaped_draws(n, seed=11):
+    """More family-4 instances with sizes, match ratio and skew drawn at random
+    around the two large shapes (alternating sparse and skewed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        if i % 2 == 0:
+            b, p = int(rng.integers(22, 26)), int(rng.integers(27, 30))
+            m = 50 * int(rng.integers(12, 20))
+            out.append(("sparse_unique64", dict(seed=200 + i, n_build=1 << b, n_probe=1 << p, match_per_mille=m)))
+        else:
+            d, p = int(rng.integers(22, 26)), int(rng.integers(27, 29))
+            z = round(float(rng.uniform(0.3, 1.5)), 2)
+            out.append(("skewed_dup32", dict(seed=200 + i, n_distinct=1 << d, n_probe=1 << p, zipf_s=z)))
+    return out
+
+
+SHAPED = SHAPED + _shaped_draws(48)
 FIXED_HASH_CLASS = 2  # GLOBAL_HASH at load factor 0.5
 
 
