@@ -157,6 +157,63 @@ def collect(path, n_instances, seed=7, reps=3, max_build_log2=22.0, max_probe_lo
                 print(f"instance {idx}: best {best}, elapsed {time.time() - t0:.0f} s", flush=True)
 
 
+def retime(path, family, classes, out, reps=3, device="cuda:0", log_every=10, time_limit_s=None):
+    """Re-time `classes` and the rule plan on every timed instance of family
+    `family`'s data file `path`, keeping the other classes' timings: for a kernel
+    change that only affects those classes. Writes `out` in the order of `path`
+    (skipped instances copied as they are), resuming after what `out` holds."""
+    import synth
+    kw = {k: v for k, v in FAMILIES[family].items() if k not in ("n_instances", "seed")}
+    with open(path) as f:
+        recs = [json.loads(line) for line in f]
+    done = 0
+    if os.path.exists(out):
+        with open(out) as f:
+            done = sum(1 for _ in f)
+    t0 = time.time()
+    with open(out, "a") as f:
+        for k in range(done, len(recs)):
+            rec = recs[k]
+            if time_limit_s and time.time() - t0 > time_limit_s:
+                print(f"time limit reached at record {k}", flush=True)
+                break
+            if not rec.get("skipped"):
+                inp = synth.selector_instance(rec["seed"], rec["idx"], device=device, **kw)
+                assert (inp.n_build, inp.n_probe) == (rec["n_build"], rec["n_probe"]), "instance drifted"
+                sb, sp = eg.stats(inp.build_keys), eg.stats(inp.probe_keys)
+                fixed = eg.join_plan(sb, sp, eg.SEL_FIXED_HASH)
+                rule = eg.join_plan(sb, sp, eg.SEL_RULE)
+                cnt = eg.join(inp.build_keys, inp.build_payload, inp.probe_keys, inp.probe_payload, fixed,
+                              count_only=True)
+                cap = max(cnt.count, 1)
+                outs = (torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device),
+                        torch.empty(cap, dtype=torch.int32, device=inp.probe_keys.device))
+                plans = {c: eg.selector_class_plan(c, sb, sp) for c in classes}
+                need = max(eg.join_workspace_size(q, inp.build_keys, inp.build_payload, inp.probe_keys,
+                                                  inp.probe_payload) for q in list(plans.values()) + [rule]
+                           if q is not None)
+                ws = torch.empty(max(need, 1), dtype=torch.uint8, device=inp.probe_keys.device)
+                kept = [t for c, t in enumerate(rec["times_ms"]) if t is not None and c not in classes]
+                best = min(kept) if kept else math.inf
+                agree = rec["all_variants_agree"]
+                for c, q in plans.items():
+                    if q is None:
+                        continue
+                    t, res = _time_join(inp, q, ws, outs, reps, budget_ms=max(20 * best, 5.0))
+                    rec["times_ms"][c] = t
+                    agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
+                rec["rule_ms"], res = _time_join(inp, rule, ws, outs, reps, budget_ms=math.inf)
+                agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
+                rec["all_variants_agree"] = bool(agree)
+                rec["retimed_classes"] = sorted(classes)
+                del inp, outs, ws
+                torch.cuda.empty_cache()
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            if k % log_every == 0:
+                print(f"record {k}: elapsed {time.time() - t0:.0f} s", flush=True)
+
+
 def load_records(paths=None):
     """Timed instances of every data file (skipped instances left out)."""
     if paths is None:
@@ -331,6 +388,7 @@ def collect_shaped(path, reps=3, device="cuda:0", log=print):
 
 def main(argv=None):
     """python -m paper_2607_04489_amd.selector collect --family F [--out PATH] [--time-limit S]
+       python -m paper_2607_04489_amd.selector retime --family F --classes 1,2,3 --out PATH
        python -m paper_2607_04489_amd.selector train [--out MODEL]
     collect resumes a partial file; train fits on the 80% split of every data
     file and prints the held-out evaluation."""
@@ -341,6 +399,11 @@ def main(argv=None):
     c.add_argument("--family", type=int, choices=sorted(FAMILIES) + [4], required=True)
     c.add_argument("--out", default=None)
     c.add_argument("--time-limit", type=float, default=None)
+    rt = sub.add_parser("retime")
+    rt.add_argument("--family", type=int, choices=sorted(FAMILIES), required=True)
+    rt.add_argument("--classes", default="1,2,3", help="comma-separated class indices")
+    rt.add_argument("--out", required=True)
+    rt.add_argument("--time-limit", type=float, default=None)
     t = sub.add_parser("train")
     t.add_argument("--out", default=MODEL_PATH)
     t.add_argument("--steps", type=int, default=2000)
@@ -353,6 +416,10 @@ def main(argv=None):
         kw = dict(FAMILIES[args.family])
         n = kw.pop("n_instances")
         collect(args.out or FAMILY_PATHS[args.family], n, time_limit_s=args.time_limit, log_every=10, **kw)
+        return
+    if args.cmd == "retime":
+        retime(FAMILY_PATHS[args.family], args.family, [int(c) for c in args.classes.split(",")], args.out,
+               time_limit_s=args.time_limit)
         return
     recs = load_records()
     train_set, test_set = split(recs, seed=0)
