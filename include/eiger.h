@@ -494,7 +494,9 @@ int eiger_join_batch_destroy(void *handle);
  * A small MLP (EIGER_SEL_FEATURES -> 64 -> 64 -> EIGER_SEL_CLASSES, ReLU) predicts
  * log2(join time in ms) of every plan class from 16 features of the two sides'
  * statistics; EIGER_SEL_LEARNED picks the feasible class with the smallest
- * prediction. This selector is this library's addition: the paper selects
+ * prediction, except that when that class is GLOBAL_HASH, a GLOBAL_HASH class of
+ * larger load factor (smaller table) predicted within 1% of it is taken instead
+ * (the largest such load factor). This selector is this library's addition: the paper selects
  * algorithms from runtime statistics (Section 4) but gives no selection model.
  * Parameters are one fp32 array: W1[16][64], b1[64], W2[64][64], b2[64],
  * W3[64][16], b3[16] (row-major, input index first). Training runs on the GPU

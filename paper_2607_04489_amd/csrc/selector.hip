@@ -26,6 +26,11 @@ constexpr ClassSpec kClasses[kOut] = {
     {EIGER_RADIX_CACHE, 10, 1, 0.3f},
 };
 
+// Predictions (log2 ms) of two GLOBAL_HASH load factors closer than log2(1.01)
+// are taken as a tie: the selector then prefers the larger load factor, which
+// halves the table's memory and its clear at no predicted cost.
+constexpr float kTieLog2 = 0.0143552929770700f;
+
 double range_of(const eiger_stats_t &s) {
   if (s.n <= 0) return 0.0;
   return static_cast<double>(static_cast<uint64_t>(s.max) - static_cast<uint64_t>(s.min)) + 1.0;
@@ -143,12 +148,23 @@ int learned_plan(const eiger_stats_t &b, const eiger_stats_t &p, eiger_plan_t *o
   for (int i = 0; i < kIn; ++i) x[i] = (x[i] - mean[i]) / stdv[i];
   host_forward(P.data(), x, y);
   int best = -1;
+  bool feasible[kOut];
   for (int c = 0; c < kOut; ++c) {
     eiger_plan_t tmp;
-    if (class_plan(c, b, p, &tmp) != EIGER_OK) continue;
+    feasible[c] = class_plan(c, b, p, &tmp) == EIGER_OK;
+    if (!feasible[c]) continue;
     if (best < 0 || y[c] < y[best]) best = c;
   }
   if (best < 0) return fail(EIGER_ERR_MODEL, "learned selector: no feasible class");
+  // Near-tie between GLOBAL_HASH load factors: take the largest load factor
+  // (the smallest table) predicted within kTieLog2 of the best.
+  if (kClasses[best].variant == EIGER_GLOBAL_HASH) {
+    const int first = best;
+    for (int c = 0; c < kOut; ++c)
+      if (feasible[c] && kClasses[c].variant == EIGER_GLOBAL_HASH && kClasses[c].lf > kClasses[best].lf &&
+          y[c] - y[first] <= kTieLog2)
+        best = c;
+  }
   set_error("");
   return class_plan(best, b, p, out);
 }

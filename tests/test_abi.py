@@ -206,6 +206,33 @@ def test_selector_load_rejects_bad_models(lib):
         eg.selector_load(bad, np.zeros(16), np.ones(16))
 
 
+def test_selector_load_factor_near_tie(lib):
+    """A GLOBAL_HASH choice moves to the largest load factor predicted within
+    1% (log2(1.01) in log2 ms) of it; other variants keep the plain argmin."""
+    import torch as T
+    from paper_2607_04489_amd import selector
+    b, s = stats(1 << 20, -(1 << 40), 1 << 40, float(1 << 20), eg.INT64), \
+        stats(1 << 22, -(1 << 40), 1 << 40, float(1 << 20), eg.INT64)
+    cases = [  # output biases of classes 1, 2, 3 (GLOBAL_HASH 0.25 / 0.5 / 0.75), 8 -> load factor / variant
+        ((3.0, 3.01, 3.02, 5.0), (eg.GLOBAL_HASH, 0.5)),
+        ((3.0, 3.02, 3.03, 5.0), (eg.GLOBAL_HASH, 0.25)),
+        ((3.0, 3.01, 3.005, 5.0), (eg.GLOBAL_HASH, 0.75)),
+        ((3.01, 3.0, 3.02, 5.0), (eg.GLOBAL_HASH, 0.5)),
+        ((3.005, 5.0, 5.0, 3.0), (eg.RADIX, 0.25)),
+    ]
+    for (b1, b2, b3, b8), want in cases:
+        params = T.zeros(6288)
+        params[6272:] = 6.0
+        params[6272 + 1], params[6272 + 2], params[6272 + 3], params[6272 + 8] = b1, b2, b3, b8
+        eg.selector_load(params, np.zeros(16), np.ones(16))
+        got = plan(b, s, eg.SEL_LEARNED)
+        assert (got.variant, round(got.load_factor, 3)) == want, ((b1, b2, b3, b8), got.describe())
+        y = params[6272:].numpy().astype(np.float32)
+        y[0] = np.inf  # DIRECT is infeasible over this key range
+        ref = eg.selector_class_plan(selector.choose(y), b, s)
+        assert (ref.variant, round(ref.load_factor, 3)) == want
+
+
 def test_selector_domain_guard_falls_back_to_rule(lib):
     """Outside the installed model's training box EIGER_SEL_LEARNED returns the
     rule plan with EIGER_PLAN_RULE_FALLBACK; inside it returns the model's class."""
