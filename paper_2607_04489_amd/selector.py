@@ -203,6 +203,7 @@ def retime(path, family, classes, out, reps=3, device="cuda:0", log_every=10, ti
                     rec["times_ms"][c] = t
                     agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
                 rec["rule_ms"], res = _time_join(inp, rule, ws, outs, reps, budget_ms=math.inf)
+                rec["rule_plan"] = rule.describe()
                 agree &= (res.count, res.checksum) == (cnt.count, cnt.checksum)
                 rec["all_variants_agree"] = bool(agree)
                 rec["retimed_classes"] = sorted(classes)
